@@ -1,0 +1,383 @@
+"""Seeded scene generators for the lattice deformation solve.
+
+Every generator takes a seed and returns a :class:`Scene`: float32 arrays in the
+layout the C-ABI accepts (array-of-structs xyz triples) plus the lattice
+description.  The recipes follow the workloads the solve is benchmarked on:
+
+* ``make_config0`` -- a 16^3 unit-spaced lattice around a sphere of radius 6,
+  2000 surface samples warped by 8 Gaussian RBF displacements (amplitude 0.8,
+  width 4) plus N(0, 0.02) noise, 50 sparse point pairs, weights 1/10/5,
+  5 GN x 10 PCG on one level.
+* ``make_config1`` -- a 64^3 lattice (h = 15.625 mm) around a noisy torus,
+  rendered into a 640x480 depth map (fx = fy = 525, cx = 320, cy = 240) under
+  a 32-centre RBF warp (amplitude 2 voxels); one dense constraint per valid
+  pixel (about 1e5), 500 sparse pairs, 3 levels x 8 GN x 20 PCG.
+* ``make_tiny`` -- small random problems for exhaustive checks.
+
+Only inputs are produced here.  The RBF warp W(x) = x + sum_k a_k
+exp(-|x - c_k|^2 / (2 sigma^2)) is the *ground truth* that makes targets; it is
+not the lattice deformation the solver fits.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, Tuple
+
+import numpy as np
+
+
+@dataclass
+class LatticeSpec:
+    """Lattice description: finest node counts, spacing, origin, hierarchy and
+    schedule (listed coarse -> fine), and the energy weights w_d, w_s, w_r."""
+
+    dims: Tuple[int, int, int]
+    spacing: float
+    origin: Tuple[float, float, float]
+    num_levels: int
+    gn_iters: Tuple[int, ...]
+    pcg_iters: Tuple[int, ...]
+    w_dense: float = 1.0
+    w_sparse: float = 10.0
+    w_arap: float = 5.0
+
+
+@dataclass
+class Scene:
+    spec: LatticeSpec
+    canon: np.ndarray          # (C,3) float32, canonical surface samples p_hat
+    target: np.ndarray         # (C,3) float32, observed points p^a
+    normal: np.ndarray         # (C,3) float32, observed unit normals n^a
+    weight: np.ndarray         # (C,)  float32, per-correspondence confidence w_c
+    sparse_canon: np.ndarray   # (S,3) float32, canonical feature positions f_hat
+    sparse_target: np.ndarray  # (S,3) float32, observed feature positions f
+    meta: Dict = field(default_factory=dict)
+
+    @property
+    def n_dense(self) -> int:
+        return int(self.canon.shape[0])
+
+    @property
+    def n_sparse(self) -> int:
+        return int(self.sparse_canon.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# ground-truth warp used to make targets
+# ---------------------------------------------------------------------------
+
+def _random_directions(rng: np.random.Generator, k: int) -> np.ndarray:
+    v = rng.normal(size=(k, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+class RBFWarp:
+    """W(x) = x + sum_k a_k exp(-|x-c_k|^2 / (2 sigma^2)) and its Jacobian."""
+
+    def __init__(self, centres: np.ndarray, amps: np.ndarray, sigma: float):
+        self.c = np.asarray(centres, np.float64)
+        self.a = np.asarray(amps, np.float64)
+        self.sigma = float(sigma)
+
+    def _phi(self, x: np.ndarray) -> np.ndarray:
+        d2 = ((x * x).sum(1)[:, None] - 2.0 * (x @ self.c.T)
+              + (self.c * self.c).sum(1)[None, :])
+        return np.exp(-np.maximum(d2, 0.0) / (2.0 * self.sigma ** 2))
+
+    def apply(self, x: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+        x = np.asarray(x, np.float64)
+        out = np.empty_like(x)
+        for s in range(0, x.shape[0], chunk):
+            xs = x[s:s + chunk]
+            out[s:s + chunk] = xs + self._phi(xs) @ self.a
+        return out
+
+    def jacobian(self, x: np.ndarray) -> np.ndarray:
+        x = np.asarray(x, np.float64)
+        phi = self._phi(x)                                   # (n,K)
+        diff = x[:, None, :] - self.c[None, :, :]            # (n,K,3)
+        grad_phi = -phi[:, :, None] * diff / self.sigma ** 2  # (n,K,3)
+        jac = np.einsum("ka,nkb->nab", self.a, grad_phi)
+        jac += np.eye(3)[None]
+        return jac
+
+    def transform_normals(self, x: np.ndarray, n: np.ndarray) -> np.ndarray:
+        jac = self.jacobian(x)
+        m = np.linalg.inv(jac).transpose(0, 2, 1)
+        out = np.einsum("nab,nb->na", m, n)
+        return out / np.linalg.norm(out, axis=1, keepdims=True)
+
+
+def _uniform_sphere(rng, k, centre, radius):
+    u = _random_directions(rng, k)
+    return np.asarray(centre)[None, :] + radius * u, u
+
+
+# ---------------------------------------------------------------------------
+# configuration 0: 16^3 sphere
+# ---------------------------------------------------------------------------
+
+def make_config0(seed: int = 0) -> Scene:
+    rng = np.random.default_rng(seed)
+    n = 16
+    spec = LatticeSpec(dims=(n, n, n), spacing=1.0, origin=(0.0, 0.0, 0.0),
+                       num_levels=1, gn_iters=(5,), pcg_iters=(10,),
+                       w_dense=1.0, w_sparse=10.0, w_arap=5.0)
+    centre = np.array([7.5, 7.5, 7.5])
+    radius = 6.0
+    canon, nhat = _uniform_sphere(rng, 2000, centre, radius)
+    centres = rng.uniform(1.5, 13.5, size=(8, 3))
+    amps = 0.8 * _random_directions(rng, 8)
+    warp = RBFWarp(centres, amps, sigma=4.0)
+    target = warp.apply(canon) + rng.normal(scale=0.02, size=canon.shape)
+    normal = warp.transform_normals(canon, nhat)
+    sp_canon, _ = _uniform_sphere(rng, 50, centre, radius)
+    sp_target = warp.apply(sp_canon) + rng.normal(scale=0.02, size=sp_canon.shape)
+    return Scene(spec=spec,
+                 canon=canon.astype(np.float32), target=target.astype(np.float32),
+                 normal=normal.astype(np.float32),
+                 weight=np.ones(canon.shape[0], np.float32),
+                 sparse_canon=sp_canon.astype(np.float32),
+                 sparse_target=sp_target.astype(np.float32),
+                 meta={"config": 0, "seed": seed, "rbf_centres": centres,
+                       "rbf_amps": amps, "rbf_sigma": 4.0})
+
+
+# ---------------------------------------------------------------------------
+# configuration 1: 64^3 torus rendered to a 640x480 depth map
+# ---------------------------------------------------------------------------
+
+CAM = dict(width=640, height=480, fx=525.0, fy=525.0, cx=320.0, cy=240.0)
+
+# Geometry constants chosen so that a seed gives roughly 1e5 valid pixels.
+CFG1_H = 0.015625           # 15.625 mm node spacing, 64 nodes ~ 1 m
+CFG1_DEPTH = 0.95           # camera distance of the torus centre (m)
+CFG1_MAJOR = 0.26           # torus major radius (m)
+CFG1_MINOR = 0.10           # torus minor radius (m)
+CFG1_TILT_DEG = 30.0        # tilt of the torus axis away from the view axis
+
+
+def _torus_points(rng, n_theta, n_phi, major, minor, noise_amp):
+    """Canonical torus points (local frame, axis = z) with a smooth random
+    perturbation of the tube radius (low-frequency signed-distance noise)."""
+    th = (np.arange(n_theta) + rng.uniform()) * (2 * np.pi / n_theta)
+    ph = (np.arange(n_phi) + rng.uniform()) * (2 * np.pi / n_phi)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    T = T.ravel()
+    P = P.ravel()
+    eta = np.zeros_like(T)
+    freqs = [(1, 1), (2, 1), (3, 2), (1, 2), (2, 3)]
+    for (m, k) in freqs:
+        eta += rng.normal() * np.sin(m * T + k * P + rng.uniform(0, 2 * np.pi))
+    eta *= noise_amp / max(np.abs(eta).max(), 1e-12)
+    rr = minor + eta
+    x = (major + rr * np.cos(P)) * np.cos(T)
+    y = (major + rr * np.cos(P)) * np.sin(T)
+    z = rr * np.sin(P)
+    return np.stack([x, y, z], axis=1)
+
+
+def _rot_x(deg):
+    a = np.deg2rad(deg)
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]], np.float64)
+
+
+def _render(points_world, cam, noise_sigma, rng):
+    """Point-splat z-buffer: nearest warped point per pixel wins.
+
+    Returns (clean depth, noisy depth, winner index) images; winner = -1 where
+    no point landed."""
+    W, H = cam["width"], cam["height"]
+    X, Y, Z = points_world[:, 0], points_world[:, 1], points_world[:, 2]
+    ok = Z > 1e-3
+    u = np.floor(cam["fx"] * X / np.where(ok, Z, 1) + cam["cx"]).astype(np.int64)
+    v = np.floor(cam["fy"] * Y / np.where(ok, Z, 1) + cam["cy"]).astype(np.int64)
+    ok &= (u >= 0) & (u < W) & (v >= 0) & (v < H)
+    idx = np.nonzero(ok)[0]
+    pix = v[idx] * W + u[idx]
+    order = np.lexsort((Z[idx], pix))
+    pix_sorted = pix[order]
+    first = np.ones(order.size, bool)
+    first[1:] = pix_sorted[1:] != pix_sorted[:-1]
+    win = idx[order[first]]
+    winpix = pix_sorted[first]
+    winner = -np.ones(W * H, np.int64)
+    winner[winpix] = win
+    clean = np.zeros(W * H, np.float64)
+    clean[winpix] = Z[win]
+    noisy = clean.copy()
+    noisy[winpix] += rng.normal(scale=noise_sigma, size=winpix.size)
+    return clean.reshape(H, W), noisy.reshape(H, W), winner.reshape(H, W)
+
+
+def _backproject(depth, cam):
+    H, W = depth.shape
+    uu, vv = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    x = (uu - cam["cx"]) / cam["fx"] * depth
+    y = (vv - cam["cy"]) / cam["fy"] * depth
+    return np.stack([x, y, depth], axis=-1)
+
+
+def _depth_normals(depth, cam, max_jump=0.02, min_cos=0.2):
+    """Normals from central differences of the back-projected depth map,
+    oriented toward the camera; invalid where a neighbour is missing, across
+    depth jumps, or at grazing angles."""
+    P = _backproject(depth, cam)
+    valid = depth > 0
+    H, W = depth.shape
+    nrm = np.zeros_like(P)
+    ok = np.zeros((H, W), bool)
+    c = (slice(1, H - 1), slice(1, W - 1))
+    dx = P[1:-1, 2:] - P[1:-1, :-2]
+    dy = P[2:, 1:-1] - P[:-2, 1:-1]
+    n = np.cross(dx, dy)
+    ln = np.linalg.norm(n, axis=-1)
+    nb = (valid[1:-1, 2:] & valid[1:-1, :-2] & valid[2:, 1:-1] & valid[:-2, 1:-1]
+          & valid[c])
+    d0 = depth[c]
+    jump = np.maximum.reduce([np.abs(depth[1:-1, 2:] - d0), np.abs(depth[1:-1, :-2] - d0),
+                              np.abs(depth[2:, 1:-1] - d0), np.abs(depth[:-2, 1:-1] - d0)])
+    good = nb & (jump < max_jump) & (ln > 0)
+    n = n / np.where(ln > 0, ln, 1)[..., None]
+    pn = np.linalg.norm(P[c], axis=-1, keepdims=True)
+    view = -P[c] / np.where(pn > 0, pn, 1.0)
+    cosv = (n * view).sum(-1)
+    n = np.where((cosv < 0)[..., None], -n, n)
+    good &= np.abs(cosv) > min_cos
+    nrm[c] = n
+    ok[c] = good
+    return nrm, ok
+
+
+def make_config1(seed: int = 0, n: int = 64, num_levels: int = 3,
+                 gn: int = 8, pcg: int = 20, n_sparse: int = 500,
+                 n_theta: int = 2400, n_phi: int = 900,
+                 rbf_centres_override=None) -> Scene:
+    rng = np.random.default_rng(seed)
+    h = CFG1_H * 64.0 / n
+    coarse_span = (2 ** (num_levels - 1)) * h * (int(np.ceil(n / 2 ** (num_levels - 1))) - 1)
+    centre = np.array([0.0, 0.0, CFG1_DEPTH])
+    origin = centre - 0.5 * coarse_span
+    spec = LatticeSpec(dims=(n, n, n), spacing=h, origin=tuple(origin.tolist()),
+                       num_levels=num_levels, gn_iters=(gn,) * num_levels,
+                       pcg_iters=(pcg,) * num_levels,
+                       w_dense=1.0, w_sparse=10.0, w_arap=5.0)
+    local = _torus_points(rng, n_theta, n_phi, CFG1_MAJOR, CFG1_MINOR, 0.5 * CFG1_H)
+    canon = local @ _rot_x(CFG1_TILT_DEG).T + centre[None, :]
+    ext = CFG1_MAJOR + CFG1_MINOR
+    if rbf_centres_override is None:
+        centres = centre[None, :] + rng.uniform(-ext, ext, size=(32, 3))
+    else:
+        centres = np.asarray(rbf_centres_override, np.float64)
+    amps = 2.0 * CFG1_H * _random_directions(rng, centres.shape[0])
+    warp = RBFWarp(centres, amps, sigma=16.0 * CFG1_H)
+    warped = warp.apply(canon)
+    clean, noisy, winner = _render(warped, CAM, 1e-3, rng)
+    nrm, ok = _depth_normals(clean, CAM)
+    ok &= noisy > 0
+    vv, uu = np.nonzero(ok)
+    P = _backproject(noisy, CAM)
+    target = P[vv, uu]
+    normal = nrm[vv, uu]
+    win = winner[vv, uu]
+    p_hat = canon[win]
+    # sparse pairs: distinct visible canonical points, targets from the warp
+    pick = rng.choice(win.size, size=min(n_sparse, win.size), replace=False)
+    sp_canon = p_hat[pick]
+    sp_target = warp.apply(sp_canon) + rng.normal(scale=1e-3, size=sp_canon.shape)
+    return Scene(spec=spec,
+                 canon=p_hat.astype(np.float32), target=target.astype(np.float32),
+                 normal=normal.astype(np.float32),
+                 weight=np.ones(p_hat.shape[0], np.float32),
+                 sparse_canon=sp_canon.astype(np.float32),
+                 sparse_target=sp_target.astype(np.float32),
+                 meta={"config": 1, "seed": seed, "valid_pixels": int(p_hat.shape[0]),
+                       "rbf_centres": centres, "rbf_amps": amps,
+                       "rbf_sigma": 16.0 * CFG1_H, "camera": CAM})
+
+
+# ---------------------------------------------------------------------------
+# small random problems
+# ---------------------------------------------------------------------------
+
+def make_tiny(seed: int = 0, dims=(4, 4, 4), spacing: float = 1.0,
+              origin=(0.0, 0.0, 0.0), n_dense: int = 40, n_sparse: int = 6,
+              num_levels: int = 1, gn: int = 3, pcg: int = 8,
+              amp: float = 0.3, weights=(1.0, 10.0, 5.0)) -> Scene:
+    """Random samples inside the lattice, targets displaced by up to ``amp``
+    (in units of the spacing), random unit normals and weights in [0.5, 1.5]."""
+    rng = np.random.default_rng(seed)
+    dims = tuple(int(d) for d in dims)
+    o = np.asarray(origin, np.float64)
+    # keep samples inside the coarsest level's extent
+    nc = np.asarray(dims)
+    for _ in range(num_levels - 1):
+        nc = (nc + 1) // 2
+    span = (nc - 1) * spacing * (2 ** (num_levels - 1))
+    canon = o + rng.uniform(0.0, 1.0, size=(n_dense, 3)) * span
+    target = canon + amp * spacing * rng.normal(size=canon.shape)
+    normal = _random_directions(rng, n_dense)
+    weight = rng.uniform(0.5, 1.5, size=n_dense)
+    sp_canon = o + rng.uniform(0.0, 1.0, size=(n_sparse, 3)) * span
+    sp_target = sp_canon + amp * spacing * rng.normal(size=sp_canon.shape)
+    spec = LatticeSpec(dims=dims, spacing=spacing, origin=tuple(o.tolist()),
+                       num_levels=num_levels, gn_iters=(gn,) * num_levels,
+                       pcg_iters=(pcg,) * num_levels,
+                       w_dense=weights[0], w_sparse=weights[1], w_arap=weights[2])
+    return Scene(spec=spec, canon=canon.astype(np.float32),
+                 target=target.astype(np.float32), normal=normal.astype(np.float32),
+                 weight=weight.astype(np.float32),
+                 sparse_canon=sp_canon.astype(np.float32),
+                 sparse_target=sp_target.astype(np.float32),
+                 meta={"config": "tiny", "seed": seed})
+
+
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def make_rigid_scene(base: Scene, Q: np.ndarray, c: np.ndarray) -> Scene:
+    """Targets and normals moved by the rigid map x -> Q x + c, without noise:
+    the lattice state t_i = Q t_hat_i + c, R_i = Q explains them exactly."""
+    Q = np.asarray(Q, np.float64)
+    c = np.asarray(c, np.float64)
+    canon = base.canon.astype(np.float64)
+    sp = base.sparse_canon.astype(np.float64)
+    return Scene(spec=base.spec, canon=base.canon,
+                 target=(canon @ Q.T + c).astype(np.float32),
+                 normal=(base.normal.astype(np.float64) @ Q.T).astype(np.float32),
+                 weight=base.weight, sparse_canon=base.sparse_canon,
+                 sparse_target=(sp @ Q.T + c).astype(np.float32),
+                 meta=dict(base.meta, rigid=True))
+
+
+def make_identity_scene(base: Scene) -> Scene:
+    """Targets equal to the canonical samples: the rest state is optimal."""
+    return Scene(spec=base.spec, canon=base.canon, target=base.canon.copy(),
+                 normal=base.normal, weight=base.weight,
+                 sparse_canon=base.sparse_canon,
+                 sparse_target=base.sparse_canon.copy(),
+                 meta=dict(base.meta, identity=True))
+
+
+def make_sequence_frame(seed: int, frame: int, n: int = 64, num_levels: int = 3,
+                        gn: int = 8, pcg: int = 20, speed_voxels: float = 0.3,
+                        n_sparse: int = 500) -> Scene:
+    """Frame ``frame`` of a deforming sequence: the config-1 torus whose RBF
+    centres move ``speed_voxels`` node spacings per frame along fixed random
+    directions (the same canonical surface for every frame of a seed)."""
+    rng = np.random.default_rng(10_000 + seed)
+    ext = CFG1_MAJOR + CFG1_MINOR
+    centre = np.array([0.0, 0.0, CFG1_DEPTH])
+    c0 = centre[None, :] + rng.uniform(-ext, ext, size=(32, 3))
+    dirs = _random_directions(rng, 32)
+    h = CFG1_H * 64.0 / n
+    centres = c0 + frame * speed_voxels * h * dirs
+    return make_config1(seed=seed, n=n, num_levels=num_levels, gn=gn, pcg=pcg,
+                        n_sparse=n_sparse, rbf_centres_override=centres)
