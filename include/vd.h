@@ -1,0 +1,224 @@
+/*
+ * vd.h -- C-ABI of the MI355X (gfx950) lattice deformation solver.
+ *
+ * The library solves, per frame, the non-rigid tracking problem of
+ * VolumeDeform (Innmann et al., "VolumeDeform: Real-time Volumetric Non-rigid
+ * Reconstruction", 2016):
+ *
+ *   Given  a regular deformation lattice with per-node positions t_i and
+ *          rotations R_i (Sec. 4), dense point-to-plane correspondences and
+ *          sparse point-to-point correspondences (Sec. 6, eqs. (2)-(3)) and
+ *          the energy weights (eq. (1)),
+ *   find   the t_i, R_i minimising E_total = w_s E_sparse + w_d E_dense +
+ *          w_r E_reg (eqs. (1)-(4)), by the flip-flop of Sec. 7.1
+ *          (positions by preconditioned CG on the normal equations, rotations
+ *          by Procrustes) over the nested coarse-to-fine hierarchy of
+ *          Sec. 7.2.
+ *
+ * Conventions shared by every call:
+ *   - Return value: VD_OK (0) or a negative VD_E* code; vd_strerror() names it.
+ *     No exception crosses the ABI.  On a validation error the handle is left
+ *     unchanged.
+ *   - Lengths are world units.  Node (a,b,c) of the finest level rests at
+ *     origin + spacing * (a,b,c) and is numbered a + nx*(b + ny*c).
+ *   - Point arrays are float32, array-of-structs xyz triples (3*n floats).
+ *     Rotations are row-major 3x3 (9 floats per node).
+ *   - `mem` says where caller pointers live: VD_MEM_HOST or VD_MEM_DEVICE
+ *     (device memory of the handle's GPU, e.g. a torch tensor's data_ptr()).
+ *   - The library owns all device memory it allocates; the caller owns every
+ *     buffer it passes.  No caller pointer is kept after a call returns.
+ *   - Work is issued on the stream given at creation (a hipStream_t passed as
+ *     void*; NULL = the null stream).  One handle must not be used by two host
+ *     threads at once.
+ *   - The global rigid pose (R, t of Sec. 4) is not part of this path: the
+ *     caller expresses targets and normals in the frame where it is the
+ *     identity.
+ */
+#ifndef VD_H
+#define VD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define VD_OK 0
+#define VD_EINVAL (-1)   /* bad argument, non-finite value or negative weight */
+#define VD_ERANGE (-2)   /* a canonical sample lies outside the coarsest level */
+#define VD_ENOMEM (-3)   /* device allocation failed */
+#define VD_EHIP (-4)     /* a HIP runtime call failed */
+#define VD_ESTATE (-5)   /* call not valid in the handle's current state */
+
+/* ---- precision modes (arithmetic type of the node vectors) -------------- */
+#define VD_FP32_FP64RED 0 /* float32 vectors, stencil and rotations; float64
+                             CG scalars and energy sums; float64 rotation
+                             refit when the float32 fit is ill-conditioned */
+#define VD_FP64 1         /* float64 everywhere */
+
+/* ---- pointer location --------------------------------------------------- */
+#define VD_MEM_HOST 0
+#define VD_MEM_DEVICE 1
+
+/* ---- creation flags ----------------------------------------------------- */
+#define VD_FLAG_GRAPH 1u /* capture each frame's schedule in a hipGraph and
+                            replay it (default launch path when set) */
+#define VD_FLAG_TRACE 2u /* record E_total after every half-step */
+
+/* ---- report bits -------------------------------------------------------- */
+#define VD_REPORT_PCG_GUARD 1u    /* a CG step size hit its zero guard */
+#define VD_REPORT_POLAR_FP64 2u   /* some rotation fits were redone in float64 */
+#define VD_REPORT_POLAR_KEEP 4u   /* some rotation fits were degenerate and kept
+                                     the previous rotation */
+
+#define VD_MAX_LEVELS 4
+#define VD_MAX_TRACE 512
+
+typedef struct vd_lattice vd_lattice;
+
+/* Lattice description.  dims[] are the finest level's node counts (>= 2);
+ * level l-1 has ceil(n_l / 2) nodes per axis and twice the spacing, all levels
+ * sharing `origin` (vertex-nested: coarse node j sits on fine node 2j).
+ * gn_iters[] and pcg_iters[] list the schedule coarse -> fine (entries beyond
+ * num_levels are ignored; zero is allowed).  Weights are >= 0. */
+typedef struct {
+  int32_t dims[3];
+  double spacing;
+  double origin[3];
+  int32_t num_levels;               /* 1 .. VD_MAX_LEVELS */
+  int32_t gn_iters[VD_MAX_LEVELS];  /* flip-flop iterations per level */
+  int32_t pcg_iters[VD_MAX_LEVELS]; /* CG iterations per position step */
+  double w_dense;                   /* w_d of eq. (1) */
+  double w_sparse;                  /* w_s */
+  double w_arap;                    /* w_r */
+  int32_t precision;                /* VD_FP32_FP64RED or VD_FP64 */
+  uint32_t flags;                   /* VD_FLAG_* */
+} vd_lattice_desc;
+
+/* Correspondences of one frame (Sec. 5, used by eqs. (2)-(3)).
+ *   canon[3n]   canonical sample positions p_hat_c (must lie inside the
+ *               coarsest level's node box)
+ *   target[3n]  observed points p_c^a
+ *   normal[3n]  observed normals n_c^a (renormalised; a zero normal gives the
+ *               row weight 0)
+ *   weight[n]   confidences w_c >= 0 (NULL: all 1)
+ *   sparse_canon[3m], sparse_target[3m]  feature pairs (f_hat_s, f_s)
+ * n or m may be 0 (the matching pointers may then be NULL). */
+typedef struct {
+  int64_t n_dense;
+  const float* canon;
+  const float* target;
+  const float* normal;
+  const float* weight;
+  int64_t n_sparse;
+  const float* sparse_canon;
+  const float* sparse_target;
+  int32_t mem; /* VD_MEM_HOST or VD_MEM_DEVICE for all pointers above */
+} vd_constraints;
+
+/* Per-frame options; a NULL opts means all zero. */
+typedef struct {
+  int32_t reset_to_rest; /* start from t = t_hat, R = I instead of the
+                            previous frame's state */
+} vd_solve_opts;
+
+/* Filled by vd_solve_frame when a report pointer is given (the call then
+ * waits for the frame to finish). */
+typedef struct {
+  double energy[4];   /* E_total, w_d E_dense, w_s E_sparse, w_r E_reg at the
+                         final finest state, eq. (1), no factor 1/2 */
+  uint32_t bits;      /* VD_REPORT_* */
+  int32_t polar_fp64; /* rotation fits redone in float64 (last frame) */
+  int32_t polar_keep; /* degenerate fits that kept the previous rotation */
+  int32_t n_trace;    /* entries used in trace[] (VD_FLAG_TRACE) */
+  double trace[VD_MAX_TRACE]; /* E_total on the current level after each
+                                 position step and each rotation step */
+} vd_solve_report;
+
+/* Create a handle: allocates every per-level device array and puts the state
+ * at rest (t = t_hat, R = I).  `stream` is a hipStream_t or NULL.  Sec. 4
+ * (lattice, regular-grid initialisation), Sec. 7.2 (hierarchy). */
+int vd_lattice_create(const vd_lattice_desc* desc, void* stream, vd_lattice** out);
+
+/* Free the handle and all its device memory.  NULL is a no-op. */
+int vd_lattice_destroy(vd_lattice* l);
+
+/* Replace the correspondences.  Copies and validates the inputs (VD_EINVAL:
+ * non-finite value or negative weight; VD_ERANGE: a canonical sample outside
+ * the coarsest level), then rebuilds, for every level, the trilinear rows of
+ * eqs. (2)-(3), the per-cell cache of B^T B and B^T b (Sec. 7.1: computed
+ * once, before CG starts) and the Jacobi preconditioner.  Waits for the
+ * validation result; the rebuild itself is queued on the stream. */
+int vd_set_constraints(vd_lattice* l, const vd_constraints* c);
+
+/* Solve one frame (Sec. 7): for each level coarse -> fine, start from the
+ * finest state injected to the level plus the prolongated increment of the
+ * previous level (then one rotation fit), and run gn_iters flip-flop
+ * iterations: a position step (pcg_iters of Jacobi-preconditioned CG on
+ * A delta = -J^T r) followed by a rotation step (per-node Procrustes).  The
+ * finest result becomes the state.  Asynchronous unless `report` is non-NULL.
+ * VD_ESTATE if no constraints were set. */
+int vd_solve_frame(vd_lattice* l, const vd_solve_opts* opts, vd_solve_report* report);
+
+/* Energy terms at the current finest state, eq. (1): out = {E_total,
+ * w_d E_dense, w_s E_sparse, w_r E_reg}.  Waits for the stream. */
+int vd_get_energy(vd_lattice* l, double out[4]);
+
+/* Copy the finest state out: pos[3N] positions t_i, rot[9N] rotations R_i
+ * (either pointer may be NULL).  Waits for the stream. */
+int vd_get_state(vd_lattice* l, float* pos, float* rot, int32_t mem);
+
+/* Overwrite the finest state (checkpoint / resume).  rot may be NULL (then
+ * R = I).  VD_EINVAL on non-finite input. */
+int vd_set_state(vd_lattice* l, const float* pos, const float* rot, int32_t mem);
+
+/* Node count and dims of a level (0 = coarsest). */
+int vd_level_info(const vd_lattice* l, int32_t level, int32_t dims[3], double* spacing);
+
+/* Text for a status code. */
+const char* vd_strerror(int code);
+
+/* ---- test entry points (unstable; for parity tests) -------------------- */
+
+/* Ap = A p on `level` for the current constraints, A = J^T J of Sec. 7.1
+ * (the paper's L + B^T B with the energy weights): p, Ap are [3N] xyz
+ * triples.  Synchronous. */
+int vd_debug_apply(vd_lattice* l, int32_t level, const float* p, float* Ap, int32_t mem);
+
+/* g = J^T r at the given level state (pos [3N], rot [9N]) and the current
+ * constraints, so that E(t + d) = E + 2 g^T d + d^T A d.  Synchronous. */
+int vd_debug_gradient(vd_lattice* l, int32_t level, const float* pos, const float* rot,
+                      float* g, int32_t mem);
+
+/* Energy terms (as vd_get_energy) at a given level state.  Synchronous. */
+int vd_debug_energy(vd_lattice* l, int32_t level, const float* pos, const float* rot,
+                    double out[4], int32_t mem);
+
+/* Jacobi preconditioner diagonal diag(A) of a level, [3N].  Synchronous. */
+int vd_debug_diag(vd_lattice* l, int32_t level, float* diag, int32_t mem);
+
+/* Rotation step on a level state: R_out[9N] = Procrustes fit of the
+ * cross-covariances of pos [3N] (Sec. 7.1), degenerate fits keeping rot_prev
+ * [9N].  Synchronous. */
+int vd_debug_rotations(vd_lattice* l, int32_t level, const float* pos, const float* rot_prev,
+                       float* rot_out, int32_t mem);
+
+/* Batched rotation fit of n cross-covariances M[9n] (row-major): R[9n] is the
+ * rotation maximising trace(R^T M) (Sec. 7.1, Procrustes).  keep[n] (may be
+ * NULL) receives 0 for a direct fit, 1 for a fit redone in float64, 2 for a
+ * degenerate M (rank <= 1), where R copies R_prev[9n] (or I if R_prev is
+ * NULL).  precision: VD_FP32_FP64RED or VD_FP64.  Synchronous, on `stream`. */
+int vd_debug_fit_rotations(const float* M, const float* R_prev, float* R, int32_t* keep,
+                           int64_t n, int32_t precision, int32_t mem, void* stream);
+
+/* Prolongation of a coarse per-node field (level-1) to `level`: out[3N_fine]
+ * = trilinear evaluation of coarse[3N_coarse] at the fine rest positions.
+ * Synchronous. */
+int vd_debug_prolong(vd_lattice* l, int32_t level, const float* coarse, float* out, int32_t mem);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VD_H */

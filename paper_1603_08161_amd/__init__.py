@@ -1,0 +1,18 @@
+"""MI355X (gfx950) implementation of the VolumeDeform lattice solve.
+
+The solver lives in the HIP library ``libvd.so`` (C-ABI: ``include/vd.h``);
+this package is its Python binding.  Importing it loads the library and fails
+loudly if it has not been built.
+"""
+
+from ._lib import (  # noqa: F401
+    EXPORTED,
+    LIB_PATH,
+    Lattice,
+    VDError,
+    fit_rotations,
+    lib,
+    strerror,
+    VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE,
+    VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP,
+)

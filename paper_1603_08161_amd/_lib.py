@@ -1,0 +1,348 @@
+"""ctypes binding of libvd.so (the C-ABI in include/vd.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Arrays may be numpy (host memory) or torch CUDA tensors (device
+memory of the handle's GPU); a call takes one kind for all its arrays.  If
+libvd.so has not been built this module raises at import time -- there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+try:  # load torch's HIP runtime first so the library shares it
+    import torch  # noqa: F401
+    _HAVE_TORCH = True
+except Exception:  # pragma: no cover
+    torch = None
+    _HAVE_TORCH = False
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvd.so")
+
+VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE = 0, -1, -2, -3, -4, -5
+VD_FP32_FP64RED, VD_FP64 = 0, 1
+VD_MEM_HOST, VD_MEM_DEVICE = 0, 1
+VD_FLAG_GRAPH, VD_FLAG_TRACE = 1, 2
+VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
+VD_MAX_LEVELS = 4
+VD_MAX_TRACE = 512
+
+EXPORTED = (
+    "vd_lattice_create", "vd_lattice_destroy", "vd_set_constraints", "vd_solve_frame",
+    "vd_get_energy", "vd_get_state", "vd_set_state", "vd_level_info", "vd_strerror",
+    "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
+    "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong",
+)
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [
+        ("dims", C.c_int32 * 3),
+        ("spacing", C.c_double),
+        ("origin", C.c_double * 3),
+        ("num_levels", C.c_int32),
+        ("gn_iters", C.c_int32 * VD_MAX_LEVELS),
+        ("pcg_iters", C.c_int32 * VD_MAX_LEVELS),
+        ("w_dense", C.c_double),
+        ("w_sparse", C.c_double),
+        ("w_arap", C.c_double),
+        ("precision", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class Constraints(C.Structure):
+    _fields_ = [
+        ("n_dense", C.c_int64),
+        ("canon", C.c_void_p),
+        ("target", C.c_void_p),
+        ("normal", C.c_void_p),
+        ("weight", C.c_void_p),
+        ("n_sparse", C.c_int64),
+        ("sparse_canon", C.c_void_p),
+        ("sparse_target", C.c_void_p),
+        ("mem", C.c_int32),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("reset_to_rest", C.c_int32)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [
+        ("energy", C.c_double * 4),
+        ("bits", C.c_uint32),
+        ("polar_fp64", C.c_int32),
+        ("polar_keep", C.c_int32),
+        ("n_trace", C.c_int32),
+        ("trace", C.c_double * VD_MAX_TRACE),
+    ]
+
+
+class VDError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+            "g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "vd_lattice_create": ([C.POINTER(LatticeDesc), vp, C.POINTER(vp)], C.c_int),
+        "vd_lattice_destroy": ([vp], C.c_int),
+        "vd_set_constraints": ([vp, C.POINTER(Constraints)], C.c_int),
+        "vd_solve_frame": ([vp, C.POINTER(SolveOpts), C.POINTER(SolveReport)], C.c_int),
+        "vd_get_energy": ([vp, dp], C.c_int),
+        "vd_get_state": ([vp, vp, vp, i32], C.c_int),
+        "vd_set_state": ([vp, vp, vp, i32], C.c_int),
+        "vd_level_info": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
+        "vd_strerror": ([C.c_int], C.c_char_p),
+        "vd_debug_apply": ([vp, i32, vp, vp, i32], C.c_int),
+        "vd_debug_gradient": ([vp, i32, vp, vp, vp, i32], C.c_int),
+        "vd_debug_energy": ([vp, i32, vp, vp, dp, i32], C.c_int),
+        "vd_debug_diag": ([vp, i32, vp, i32], C.c_int),
+        "vd_debug_rotations": ([vp, i32, vp, vp, vp, i32], C.c_int),
+        "vd_debug_fit_rotations": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
+        "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return _lib.vd_strerror(code).decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != VD_OK:
+        raise VDError(code, what)
+
+
+def _is_device(a) -> bool:
+    return _HAVE_TORCH and isinstance(a, torch.Tensor) and a.is_cuda
+
+
+def _prep(arrays, allow_none=()):
+    """Return (pointers, mem, keepalive) for a list of arrays of one kind."""
+    present = [a for a in arrays if a is not None]
+    dev = [_is_device(a) for a in present]
+    if any(dev) and not all(dev):
+        raise ValueError("mix of host and device arrays in one call")
+    mem = VD_MEM_DEVICE if (present and dev[0]) else VD_MEM_HOST
+    ptrs, keep = [], []
+    for a in arrays:
+        if a is None:
+            ptrs.append(None)
+            continue
+        if mem == VD_MEM_DEVICE:
+            if a.dtype != torch.float32 or not a.is_contiguous():
+                raise ValueError("device arrays must be contiguous float32 tensors")
+            ptrs.append(a.data_ptr())
+            keep.append(a)
+        else:
+            h = np.ascontiguousarray(a, dtype=np.float32)
+            keep.append(h)
+            ptrs.append(h.ctypes.data)
+    return ptrs, mem, keep
+
+
+def _host(a) -> np.ndarray:
+    if _HAVE_TORCH and isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _current_stream() -> int:
+    if _HAVE_TORCH and torch.cuda.is_available():
+        return int(torch.cuda.current_stream().cuda_stream)
+    return 0
+
+
+class Lattice:
+    """A lattice handle (vd_lattice*)."""
+
+    def __init__(self, dims, spacing, origin, num_levels=1, gn_iters=(5,), pcg_iters=(10,),
+                 w_dense=1.0, w_sparse=10.0, w_arap=5.0, precision="fp32",
+                 graph=False, trace=False, stream: Optional[int] = None):
+        d = LatticeDesc()
+        for k in range(3):
+            d.dims[k] = int(dims[k])
+            d.origin[k] = float(origin[k])
+        d.spacing = float(spacing)
+        d.num_levels = int(num_levels)
+        for k in range(VD_MAX_LEVELS):
+            d.gn_iters[k] = int(gn_iters[k]) if k < len(gn_iters) else 0
+            d.pcg_iters[k] = int(pcg_iters[k]) if k < len(pcg_iters) else 0
+        d.w_dense, d.w_sparse, d.w_arap = float(w_dense), float(w_sparse), float(w_arap)
+        d.precision = VD_FP64 if precision == "fp64" else VD_FP32_FP64RED
+        d.flags = (VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
+        self.desc = d
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = C.c_void_p()
+        _check(_lib.vd_lattice_create(C.byref(d), C.c_void_p(self.stream), C.byref(h)),
+               "vd_lattice_create")
+        self._h = h
+        self.num_levels = int(num_levels)
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        return cls(spec.dims, spec.spacing, spec.origin, spec.num_levels, spec.gn_iters,
+                   spec.pcg_iters, spec.w_dense, spec.w_sparse, spec.w_arap, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.vd_lattice_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def level_info(self, level: int) -> Tuple[Tuple[int, int, int], float]:
+        dims = (C.c_int32 * 3)()
+        h = C.c_double()
+        _check(_lib.vd_level_info(self._h, level, dims, C.byref(h)), "vd_level_info")
+        return (dims[0], dims[1], dims[2]), h.value
+
+    def n_nodes(self, level: int = -1) -> int:
+        lvl = self.num_levels - 1 if level < 0 else level
+        d, _ = self.level_info(lvl)
+        return d[0] * d[1] * d[2]
+
+    def set_constraints(self, canon, target, normal, weight=None, sparse_canon=None,
+                        sparse_target=None) -> None:
+        ptrs, mem, keep = _prep([canon, target, normal, weight, sparse_canon, sparse_target])
+        c = Constraints()
+        c.n_dense = 0 if canon is None else int(canon.shape[0])
+        c.canon, c.target, c.normal, c.weight = ptrs[0], ptrs[1], ptrs[2], ptrs[3]
+        c.n_sparse = 0 if sparse_canon is None else int(sparse_canon.shape[0])
+        c.sparse_canon, c.sparse_target = ptrs[4], ptrs[5]
+        c.mem = mem
+        _check(_lib.vd_set_constraints(self._h, C.byref(c)), "vd_set_constraints")
+        del keep
+
+    def set_scene(self, scene) -> None:
+        self.set_constraints(scene.canon, scene.target, scene.normal, scene.weight,
+                             scene.sparse_canon, scene.sparse_target)
+
+    def solve_frame(self, reset: bool = False, report: bool = False):
+        o = SolveOpts()
+        o.reset_to_rest = 1 if reset else 0
+        if not report:
+            _check(_lib.vd_solve_frame(self._h, C.byref(o), None), "vd_solve_frame")
+            return None
+        r = SolveReport()
+        _check(_lib.vd_solve_frame(self._h, C.byref(o), C.byref(r)), "vd_solve_frame")
+        return {"energy": np.array(r.energy[:]), "bits": int(r.bits),
+                "polar_fp64": int(r.polar_fp64), "polar_keep": int(r.polar_keep),
+                "trace": np.array(r.trace[:r.n_trace])}
+
+    def get_energy(self) -> np.ndarray:
+        out = (C.c_double * 4)()
+        _check(_lib.vd_get_energy(self._h, out), "vd_get_energy")
+        return np.array(out[:])
+
+    def get_state(self):
+        n = self.n_nodes()
+        pos = np.empty((n, 3), np.float32)
+        rot = np.empty((n, 3, 3), np.float32)
+        _check(_lib.vd_get_state(self._h, pos.ctypes.data, rot.ctypes.data, VD_MEM_HOST),
+               "vd_get_state")
+        return pos, rot
+
+    def set_state(self, pos, rot=None) -> None:
+        ptrs, mem, keep = _prep([pos, rot])
+        _check(_lib.vd_set_state(self._h, ptrs[0], ptrs[1], mem), "vd_set_state")
+        del keep
+
+    # ---- test entry points ------------------------------------------
+    def debug_apply(self, level: int, p) -> np.ndarray:
+        n = self.n_nodes(level)
+        p = _host(p)
+        out = np.empty((n, 3), np.float32)
+        _check(_lib.vd_debug_apply(self._h, level, p.ctypes.data, out.ctypes.data, VD_MEM_HOST),
+               "vd_debug_apply")
+        return out
+
+    def debug_gradient(self, level: int, pos, rot) -> np.ndarray:
+        n = self.n_nodes(level)
+        pos, rot = _host(pos), _host(rot)
+        out = np.empty((n, 3), np.float32)
+        _check(_lib.vd_debug_gradient(self._h, level, pos.ctypes.data, rot.ctypes.data,
+                                      out.ctypes.data, VD_MEM_HOST), "vd_debug_gradient")
+        return out
+
+    def debug_energy(self, level: int, pos, rot) -> np.ndarray:
+        pos, rot = _host(pos), _host(rot)
+        out = (C.c_double * 4)()
+        _check(_lib.vd_debug_energy(self._h, level, pos.ctypes.data, rot.ctypes.data, out,
+                                    VD_MEM_HOST), "vd_debug_energy")
+        return np.array(out[:])
+
+    def debug_diag(self, level: int) -> np.ndarray:
+        n = self.n_nodes(level)
+        out = np.empty((n, 3), np.float32)
+        _check(_lib.vd_debug_diag(self._h, level, out.ctypes.data, VD_MEM_HOST), "vd_debug_diag")
+        return out
+
+    def debug_rotations(self, level: int, pos, rot_prev) -> np.ndarray:
+        n = self.n_nodes(level)
+        pos, rot_prev = _host(pos), _host(rot_prev)
+        out = np.empty((n, 3, 3), np.float32)
+        _check(_lib.vd_debug_rotations(self._h, level, pos.ctypes.data, rot_prev.ctypes.data,
+                                       out.ctypes.data, VD_MEM_HOST), "vd_debug_rotations")
+        return out
+
+    def debug_prolong(self, level: int, coarse) -> np.ndarray:
+        n = self.n_nodes(level)
+        coarse = _host(coarse)
+        out = np.empty((n, 3), np.float32)
+        _check(_lib.vd_debug_prolong(self._h, level, coarse.ctypes.data, out.ctypes.data,
+                                     VD_MEM_HOST), "vd_debug_prolong")
+        return out
+
+
+def fit_rotations(M, R_prev=None, precision: str = "fp32", stream: Optional[int] = None):
+    """Batched Procrustes fit (host arrays): returns (R (n,3,3), code (n,))."""
+    M = np.ascontiguousarray(M, np.float32).reshape(-1, 9)
+    n = M.shape[0]
+    Rp = None if R_prev is None else np.ascontiguousarray(R_prev, np.float32).reshape(-1, 9)
+    R = np.empty((n, 9), np.float32)
+    code = np.empty(n, np.int32)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_debug_fit_rotations(M.ctypes.data, None if Rp is None else Rp.ctypes.data,
+                                       R.ctypes.data, code.ctypes.data, n,
+                                       VD_FP64 if precision == "fp64" else VD_FP32_FP64RED,
+                                       VD_MEM_HOST, C.c_void_p(s)), "vd_debug_fit_rotations")
+    return R.reshape(n, 3, 3), code

@@ -1,0 +1,838 @@
+// Host side of the C-ABI declared in include/vd.h: the lattice handle, the
+// per-frame constraint build and the flip-flop schedule of Sec. 7.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/vd.h"
+#include "vd_device.h"
+#include "vd_kernels.h"
+
+namespace vd {
+namespace {
+
+#define VD_TRY(expr)                                  \
+  do {                                                \
+    if ((expr) != hipSuccess) return VD_EHIP;         \
+  } while (0)
+
+#define VD_CHECK(expr)                                \
+  do {                                                \
+    int rc_ = (expr);                                 \
+    if (rc_ != VD_OK) return rc_;                     \
+  } while (0)
+
+inline int blocks_of(int64_t n) { return (int)((n + 255) / 256); }
+
+// Device allocations owned by a handle.
+class Pool {
+ public:
+  ~Pool() { release_all(); }
+  template <typename P>
+  int alloc(P** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    if (hipMalloc(&q, count * sizeof(P)) != hipSuccess) {
+      (void)hipGetLastError();
+      return VD_ENOMEM;
+    }
+    ptrs_.push_back(q);
+    *p = static_cast<P*>(q);
+    return VD_OK;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(ptrs_.begin(), ptrs_.end(), p);
+    if (it != ptrs_.end()) {
+      (void)hipFree(p);
+      ptrs_.erase(it);
+    }
+  }
+  void release_all() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+  }
+
+ private:
+  std::vector<void*> ptrs_;
+};
+
+template <typename T>
+struct LevelData {
+  int nx = 0, ny = 0, nz = 0, N = 0, ncell = 0;
+  double h = 0;
+  T *d = nullptr, *r = nullptr, *pa = nullptr, *pb = nullptr, *ap = nullptr, *dinv = nullptr,
+    *bnode = nullptr, *base = nullptr, *rot = nullptr;
+  int* cell_map = nullptr;
+  Scalars* sc = nullptr;
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+  int cap_partials = 0;  // doubles
+  // constraint rows and cell cache
+  int cap_rows = 0, cap_cells = 0;
+  int *row_cell = nullptr, *sorted = nullptr, *seg_start = nullptr, *active_cell = nullptr;
+  T *row_f = nullptr, *row_sn = nullptr, *row_rho = nullptr, *K = nullptr, *bcell = nullptr;
+  int ntiles = 0;
+
+  LevelView<T> view(double wr) const {
+    LevelView<T> v;
+    v.nx = nx; v.ny = ny; v.nz = nz; v.N = N;
+    v.h = (T)h; v.wr = (T)wr;
+    v.d = d; v.r = r; v.ap = ap; v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
+    v.cell_map = cell_map; v.K = K; v.sc = sc; v.partials = partials; v.counter = counter;
+    return v;
+  }
+  RowView<T> rows_view(int rows, int n_dense) const {
+    RowView<T> v;
+    v.rows = rows; v.n_dense = n_dense; v.cell = row_cell; v.f = row_f; v.sn = row_sn;
+    v.rho = row_rho; v.sorted = sorted; v.seg_start = seg_start; v.bcell = bcell;
+    v.active_cell = active_cell;
+    return v;
+  }
+};
+
+int bits_for(int n) {
+  int b = 1;
+  while ((1ll << b) < (long long)n) ++b;
+  return b;
+}
+
+}  // namespace
+
+class ISolver {
+ public:
+  virtual ~ISolver() {}
+  virtual int init() = 0;
+  virtual int set_constraints(const vd_constraints* c) = 0;
+  virtual int solve_frame(const vd_solve_opts* o, vd_solve_report* r) = 0;
+  virtual int get_energy(double out[4]) = 0;
+  virtual int get_state(float* pos, float* rot, int mem) = 0;
+  virtual int set_state(const float* pos, const float* rot, int mem) = 0;
+  virtual int level_info(int level, int dims[3], double* h) const = 0;
+  virtual int debug_apply(int level, const float* p, float* ap, int mem) = 0;
+  virtual int debug_gradient(int level, const float* pos, const float* rot, float* g, int mem) = 0;
+  virtual int debug_energy(int level, const float* pos, const float* rot, double out[4], int mem) = 0;
+  virtual int debug_diag(int level, float* diag, int mem) = 0;
+  virtual int debug_rotations(int level, const float* pos, const float* rot_prev, float* rot_out,
+                              int mem) = 0;
+  virtual int debug_prolong(int level, const float* coarse, float* out, int mem) = 0;
+};
+
+template <typename T>
+class Solver final : public ISolver {
+ public:
+  Solver(const vd_lattice_desc& d, hipStream_t s) : desc_(d), stream_(s) {}
+  ~Solver() override {
+    if (graph_exec_[0]) (void)hipGraphExecDestroy(graph_exec_[0]);
+    if (graph_exec_[1]) (void)hipGraphExecDestroy(graph_exec_[1]);
+    if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
+    if (h_flags_) (void)hipHostFree(h_flags_);
+    if (h_sc_) (void)hipHostFree(h_sc_);
+    pool_.release_all();
+  }
+
+  int init() override {
+    L_ = desc_.num_levels;
+    lv_.resize(L_);
+    int dims[3] = {desc_.dims[0], desc_.dims[1], desc_.dims[2]};
+    double h = desc_.spacing;
+    for (int l = L_ - 1; l >= 0; --l) {
+      LevelData<T>& v = lv_[l];
+      v.nx = dims[0]; v.ny = dims[1]; v.nz = dims[2];
+      if (v.nx < 2 || v.ny < 2 || v.nz < 2) return VD_EINVAL;
+      const int64_t N = (int64_t)v.nx * v.ny * v.nz;
+      if (N > (1ll << 30)) return VD_EINVAL;
+      v.N = (int)N;
+      v.h = h;
+      v.ncell = (v.nx - 1) * (v.ny - 1) * (v.nz - 1);
+      v.ntiles = ((v.nx + kTX - 1) / kTX) * ((v.ny + kTY - 1) / kTY) * ((v.nz + kTZ - 1) / kTZ);
+      for (int k = 0; k < 3; ++k) dims[k] = (dims[k] + 1) / 2;
+      h *= 2.0;
+    }
+    for (int l = 0; l < L_; ++l) {
+      LevelData<T>& v = lv_[l];
+      const size_t N = v.N;
+      VD_CHECK(pool_.alloc(&v.d, 3 * N));
+      VD_CHECK(pool_.alloc(&v.r, 3 * N));
+      VD_CHECK(pool_.alloc(&v.pa, 3 * N));
+      VD_CHECK(pool_.alloc(&v.pb, 3 * N));
+      VD_CHECK(pool_.alloc(&v.ap, 3 * N));
+      VD_CHECK(pool_.alloc(&v.dinv, 3 * N));
+      VD_CHECK(pool_.alloc(&v.bnode, 3 * N));
+      VD_CHECK(pool_.alloc(&v.base, 3 * N));
+      VD_CHECK(pool_.alloc(&v.rot, 9 * N));
+      VD_CHECK(pool_.alloc(&v.cell_map, (size_t)v.ncell));
+      VD_CHECK(pool_.alloc(&v.sc, 1));
+      VD_CHECK(pool_.alloc(&v.counter, 1));
+      VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
+      VD_TRY(hipMemsetAsync(v.counter, 0, sizeof(unsigned), stream_));
+      VD_CHECK(ensure_partials(v, 0));
+    }
+    VD_CHECK(pool_.alloc(&d_flags_, 4));
+    VD_TRY(hipHostMalloc((void**)&h_flags_, 4 * sizeof(int), hipHostMallocDefault));
+    VD_TRY(hipHostMalloc((void**)&h_sc_, sizeof(Scalars), hipHostMallocDefault));
+    VD_TRY(launch_set_rest<T>(finest().view(desc_.w_arap), stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  // ---------------------------------------------------------------------
+  int set_constraints(const vd_constraints* c) override {
+    if (!c) return VD_EINVAL;
+    if (c->n_dense < 0 || c->n_sparse < 0) return VD_EINVAL;
+    if (c->n_dense + 3 * c->n_sparse > (1ll << 30)) return VD_EINVAL;
+    if (c->n_dense > 0 && (!c->canon || !c->target || !c->normal)) return VD_EINVAL;
+    if (c->n_sparse > 0 && (!c->sparse_canon || !c->sparse_target)) return VD_EINVAL;
+    if (c->mem != VD_MEM_HOST && c->mem != VD_MEM_DEVICE) return VD_EINVAL;
+    const int C = (int)c->n_dense, S = (int)c->n_sparse;
+    // stage the inputs (the caller's buffers are not kept)
+    VD_CHECK(ensure_staging(C, S));
+    const hipMemcpyKind kind = c->mem == VD_MEM_HOST ? hipMemcpyHostToDevice
+                                                     : hipMemcpyDeviceToDevice;
+    if (C > 0) {
+      VD_TRY(hipMemcpyAsync(st_canon_, c->canon, 12ull * C, kind, stream_));
+      VD_TRY(hipMemcpyAsync(st_target_, c->target, 12ull * C, kind, stream_));
+      VD_TRY(hipMemcpyAsync(st_normal_, c->normal, 12ull * C, kind, stream_));
+      if (c->weight) VD_TRY(hipMemcpyAsync(st_weight_, c->weight, 4ull * C, kind, stream_));
+    }
+    if (S > 0) {
+      VD_TRY(hipMemcpyAsync(st_scanon_, c->sparse_canon, 12ull * S, kind, stream_));
+      VD_TRY(hipMemcpyAsync(st_starget_, c->sparse_target, 12ull * S, kind, stream_));
+    }
+    RawConstraints raw;
+    raw.canon = st_canon_; raw.target = st_target_; raw.normal = st_normal_;
+    raw.weight = c->weight ? st_weight_ : nullptr;
+    raw.sparse_canon = st_scanon_; raw.sparse_target = st_starget_;
+    raw.n_dense = C; raw.n_sparse = S;
+    // validate before touching any per-level structure
+    VD_TRY(hipMemsetAsync(d_flags_, 0, sizeof(int), stream_));
+    const LevelData<T>& c0 = lv_[0];
+    VD_TRY(launch_validate(raw, c0.nx, c0.ny, c0.nz, c0.h, desc_.origin, d_flags_, stream_));
+    VD_TRY(hipMemcpyAsync(h_flags_, d_flags_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    if (h_flags_[0] & 1) return VD_EINVAL;
+    if (h_flags_[0] & 2) return VD_ERANGE;
+    // per-level rows, binning and cell cache
+    const int rows = C + 3 * S;
+    VD_CHECK(ensure_rows(rows));
+    for (int l = 0; l < L_; ++l) {
+      LevelData<T>& v = lv_[l];
+      const LevelView<T> V = v.view(desc_.w_arap);
+      const RowView<T> R = v.rows_view(rows, C);
+      VD_TRY(launch_rows<T>(raw, V, R, desc_.origin, desc_.w_dense, desc_.w_sparse, keys_in_,
+                            vals_in_, stream_));
+      VD_TRY(sort_pairs(sort_temp_, sort_temp_bytes_, keys_in_, keys_out_, vals_in_, v.sorted,
+                        rows, bits_for(v.ncell), stream_));
+      VD_TRY(launch_heads(keys_out_, rows, heads_, stream_));
+      VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, heads_, scan_, rows, stream_));
+      VD_TRY(launch_segments<T>(V, R, keys_out_, scan_, v.cell_map, v.ncell, stream_));
+      VD_TRY(launch_build_cells<T>(V, R, v.K, std::min(v.cap_cells, 8192), stream_));
+      VD_TRY(launch_assemble_nodes<T>(V, R, stream_));
+      VD_TRY(launch_reset_counters(v.sc, rows, C, 1, stream_));
+    }
+    rows_ = rows;
+    n_dense_ = C;
+    have_constraints_ = true;
+    energy_fresh_ = false;
+    return VD_OK;
+  }
+
+  // ---------------------------------------------------------------------
+  int solve_frame(const vd_solve_opts* o, vd_solve_report* rep) override {
+    if (!have_constraints_) return VD_ESTATE;
+    const int reset = (o && o->reset_to_rest) ? 1 : 0;
+    if (desc_.flags & VD_FLAG_GRAPH) {
+      VD_CHECK(run_graph(reset));
+    } else {
+      VD_CHECK(enqueue_frame(reset, stream_));
+    }
+    energy_fresh_ = true;
+    if (rep) {
+      std::memset(rep, 0, sizeof(*rep));
+      VD_TRY(hipStreamSynchronize(stream_));
+      for (int l = 0; l < L_; ++l) {
+        VD_TRY(hipMemcpy(h_sc_, lv_[l].sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+        if (h_sc_->guard_hits) rep->bits |= VD_REPORT_PCG_GUARD;
+        rep->polar_fp64 += h_sc_->polar_fp64;
+        rep->polar_keep += h_sc_->polar_keep;
+        for (int k = 0; k < h_sc_->n_trace && rep->n_trace < VD_MAX_TRACE; ++k)
+          rep->trace[rep->n_trace++] = h_sc_->trace[k];
+        if (l == L_ - 1)
+          for (int k = 0; k < 4; ++k) rep->energy[k] = h_sc_->energy[k];
+      }
+      if (rep->polar_fp64) rep->bits |= VD_REPORT_POLAR_FP64;
+      if (rep->polar_keep) rep->bits |= VD_REPORT_POLAR_KEEP;
+    }
+    return VD_OK;
+  }
+
+  int get_energy(double out[4]) override {
+    if (!out) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    LevelData<T>& F = finest();
+    if (!energy_fresh_) {
+      VD_TRY(launch_energy<T>(F.view(desc_.w_arap), F.rows_view(rows_, n_dense_), F.cap_rows, 0,
+                              stream_));
+      energy_fresh_ = true;
+    }
+    VD_TRY(hipMemcpyAsync(h_sc_, F.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
+    return VD_OK;
+  }
+
+  int get_state(float* pos, float* rot, int mem) override {
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    if (mem == VD_MEM_DEVICE) {
+      VD_TRY(launch_state_io<T>(F.view(desc_.w_arap), desc_.origin, pos, rot, nullptr, nullptr, 0,
+                                d_flags_, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+      return VD_OK;
+    }
+    VD_CHECK(ensure_debug());
+    float* dpos = pos ? dbg_f_ : nullptr;
+    float* drot = rot ? dbg_f_ + 3 * N : nullptr;
+    VD_TRY(launch_state_io<T>(F.view(desc_.w_arap), desc_.origin, dpos, drot, nullptr, nullptr, 0,
+                              d_flags_, stream_));
+    if (pos) VD_TRY(hipMemcpyAsync(pos, dpos, 12 * N, hipMemcpyDeviceToHost, stream_));
+    if (rot) VD_TRY(hipMemcpyAsync(rot, drot, 36 * N, hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  int set_state(const float* pos, const float* rot, int mem) override {
+    if (!pos) return VD_EINVAL;
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    const float* dpos = pos;
+    const float* drot = rot;
+    VD_CHECK(ensure_debug());
+    if (mem == VD_MEM_HOST) {
+      VD_TRY(hipMemcpyAsync(dbg_f_, pos, 12 * N, hipMemcpyHostToDevice, stream_));
+      dpos = dbg_f_;
+      if (rot) {
+        VD_TRY(hipMemcpyAsync(dbg_f_ + 3 * N, rot, 36 * N, hipMemcpyHostToDevice, stream_));
+        drot = dbg_f_ + 3 * N;
+      }
+    }
+    VD_TRY(hipMemsetAsync(d_flags_, 0, sizeof(int), stream_));
+    VD_TRY(launch_check_finite(dpos, 3 * N, d_flags_, stream_));
+    if (drot) VD_TRY(launch_check_finite(drot, 9 * N, d_flags_, stream_));
+    VD_TRY(hipMemcpyAsync(h_flags_, d_flags_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    if (h_flags_[0]) return VD_EINVAL;
+    VD_TRY(launch_state_io<T>(F.view(desc_.w_arap), desc_.origin, nullptr, nullptr, dpos, drot, 1,
+                              d_flags_, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    energy_fresh_ = false;
+    return VD_OK;
+  }
+
+  int level_info(int level, int dims[3], double* h) const override {
+    if (level < 0 || level >= L_) return VD_EINVAL;
+    const LevelData<T>& v = lv_[level];
+    if (dims) { dims[0] = v.nx; dims[1] = v.ny; dims[2] = v.nz; }
+    if (h) *h = v.h;
+    return VD_OK;
+  }
+
+  // ---- test entry points ----------------------------------------------
+  int debug_apply(int level, const float* p, float* ap, int mem) override {
+    if (level < 0 || level >= L_ || !p || !ap) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    VD_CHECK(ensure_debug());
+    LevelData<T>& v = lv_[level];
+    const int N = v.N;
+    VD_CHECK(upload_aos(p, 3 * N, mem));
+    VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, N, stream_));
+    VD_TRY(launch_stencil<T>(kModeApply, v.view(desc_.w_arap), dbg_t1_, dbg_t2_, nullptr, nullptr,
+                             stream_));
+    VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
+    return download_aos(ap, 3 * N, mem);
+  }
+
+  int debug_gradient(int level, const float* pos, const float* rot, float* g, int mem) override {
+    if (level < 0 || level >= L_ || !pos || !rot || !g) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    LevelView<T> V;
+    VD_CHECK(scratch_view(level, pos, rot, mem, &V));
+    const int N = V.N;
+    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, nullptr, nullptr, stream_));
+    VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
+    return download_aos(g, 3 * N, mem);
+  }
+
+  int debug_energy(int level, const float* pos, const float* rot, double out[4], int mem) override {
+    if (level < 0 || level >= L_ || !pos || !rot || !out) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    LevelView<T> V;
+    VD_CHECK(scratch_view(level, pos, rot, mem, &V));
+    LevelData<T>& v = lv_[level];
+    VD_TRY(launch_energy<T>(V, v.rows_view(rows_, n_dense_), v.cap_rows, 0, stream_));
+    VD_TRY(hipMemcpyAsync(h_sc_, v.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
+    if (level == L_ - 1) energy_fresh_ = false;
+    return VD_OK;
+  }
+
+  int debug_diag(int level, float* diag, int mem) override {
+    if (level < 0 || level >= L_ || !diag) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    VD_CHECK(ensure_debug());
+    LevelData<T>& v = lv_[level];
+    const int N = v.N;
+    std::vector<T> h(3 * (size_t)N);
+    VD_TRY(hipMemcpyAsync(h.data(), v.dinv, sizeof(T) * 3 * N, hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    std::vector<float> out(3 * (size_t)N);
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const double di = (double)h[(size_t)k * N + i];
+        out[3 * (size_t)i + k] = di > 0 ? (float)(1.0 / di) : 0.0f;
+      }
+    if (mem == VD_MEM_HOST) {
+      std::memcpy(diag, out.data(), out.size() * sizeof(float));
+    } else {
+      VD_TRY(hipMemcpy(diag, out.data(), out.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return VD_OK;
+  }
+
+  int debug_rotations(int level, const float* pos, const float* rot_prev, float* rot_out,
+                      int mem) override {
+    if (level < 0 || level >= L_ || !pos || !rot_prev || !rot_out) return VD_EINVAL;
+    LevelView<T> V;
+    VD_CHECK(scratch_view(level, pos, rot_prev, mem, &V));
+    const size_t N = V.N;
+    VD_TRY(launch_polar<T>(V, V.d, V.rot, V.rot, stream_));
+    float* drot = dbg_f_ + 3 * N;
+    VD_TRY(launch_state_io<T>(V, desc_.origin, nullptr, drot, nullptr, nullptr, 0, d_flags_,
+                              stream_));
+    if (mem == VD_MEM_HOST) {
+      VD_TRY(hipMemcpyAsync(rot_out, drot, 36 * N, hipMemcpyDeviceToHost, stream_));
+    } else {
+      VD_TRY(hipMemcpyAsync(rot_out, drot, 36 * N, hipMemcpyDeviceToDevice, stream_));
+    }
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  int debug_prolong(int level, const float* coarse, float* out, int mem) override {
+    if (level < 1 || level >= L_ || !coarse || !out) return VD_EINVAL;
+    VD_CHECK(ensure_debug());
+    LevelData<T>& c = lv_[level - 1];
+    LevelData<T>& f = lv_[level];
+    VD_CHECK(upload_aos(coarse, 3 * c.N, mem));
+    VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, c.N, stream_));
+    VD_TRY(launch_prolong_add<T>(c.view(desc_.w_arap), f.view(desc_.w_arap), dbg_t1_, nullptr,
+                                 dbg_t2_, 0, stream_));
+    VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, f.N, stream_));
+    return download_aos(out, 3 * f.N, mem);
+  }
+
+ private:
+  LevelData<T>& finest() { return lv_[L_ - 1]; }
+
+  // The frame's schedule (Sec. 7.1 flip-flop inside the Sec. 7.2 hierarchy),
+  // queued on `s`.
+  int enqueue_frame(int reset, hipStream_t s) {
+    const double wr = desc_.w_arap;
+    const bool trace = (desc_.flags & VD_FLAG_TRACE) != 0;
+    LevelData<T>& F = finest();
+    if (reset) VD_TRY(launch_set_rest<T>(F.view(wr), s));
+    for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters(lv_[l].sc, -1, -1, 1, s));
+    for (int l = 0; l < L_; ++l) {
+      LevelData<T>& v = lv_[l];
+      const LevelView<T> V = v.view(wr);
+      const RowView<T> R = v.rows_view(rows_, n_dense_);
+      if (l < L_ - 1) VD_TRY(launch_inject<T>(F.view(wr), V, 1 << (L_ - 1 - l), s));
+      if (l > 0) {
+        LevelData<T>& c = lv_[l - 1];
+        VD_TRY(launch_prolong_add<T>(c.view(wr), V, c.d, c.base, v.d, 1, s));
+        VD_TRY(launch_polar<T>(V, v.d, v.rot, v.rot, s));
+      }
+      const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
+      for (int k = 0; k < gn; ++k) {
+        VD_TRY(launch_stencil<T>(kModeRhs, V, nullptr, nullptr, nullptr, nullptr, s));
+        for (int m = 0; m < pcg; ++m) {
+          T* p_old = (m % 2 == 0) ? v.pa : v.pb;
+          T* p_new = (m % 2 == 0) ? v.pb : v.pa;
+          VD_TRY(launch_stencil<T>(kModePcg, V, nullptr, nullptr, p_old, p_new, s));
+          VD_TRY(launch_update<T>(V, p_new, s));
+        }
+        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, 1, s));
+        VD_TRY(launch_polar<T>(V, v.d, v.rot, v.rot, s));
+        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, 1, s));
+      }
+    }
+    VD_TRY(launch_energy<T>(F.view(wr), F.rows_view(rows_, n_dense_), F.cap_rows, 0, s));
+    return VD_OK;
+  }
+
+  int run_graph(int reset) {
+    if (graph_gen_[reset] != alloc_gen_ || !graph_exec_[reset]) {
+      if (graph_exec_[reset]) {
+        VD_TRY(hipGraphExecDestroy(graph_exec_[reset]));
+        graph_exec_[reset] = nullptr;
+      }
+      if (!capture_stream_)
+        VD_TRY(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
+      VD_TRY(hipStreamSynchronize(stream_));
+      hipGraph_t g = nullptr;
+      VD_TRY(hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue_frame(reset, capture_stream_);
+      const hipError_t e = hipStreamEndCapture(capture_stream_, &g);
+      if (rc != VD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return VD_EHIP;
+      const hipError_t ei = hipGraphInstantiate(&graph_exec_[reset], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return VD_EHIP;
+      graph_gen_[reset] = alloc_gen_;
+    }
+    VD_TRY(hipGraphLaunch(graph_exec_[reset], stream_));
+    return VD_OK;
+  }
+
+  int ensure_partials(LevelData<T>& v, int rows) {
+    const int need = 4 * std::max({v.ntiles, blocks_of(v.N), blocks_of(rows) + blocks_of(v.N)});
+    if (need <= v.cap_partials) return VD_OK;
+    pool_.release(v.partials);
+    VD_CHECK(pool_.alloc(&v.partials, (size_t)need));
+    v.cap_partials = need;
+    ++alloc_gen_;
+    return VD_OK;
+  }
+
+  int ensure_staging(int C, int S) {
+    if (C > cap_dense_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(st_canon_); pool_.release(st_target_); pool_.release(st_normal_);
+      pool_.release(st_weight_);
+      const size_t cap = (size_t)C + C / 4 + 64;
+      VD_CHECK(pool_.alloc(&st_canon_, 3 * cap));
+      VD_CHECK(pool_.alloc(&st_target_, 3 * cap));
+      VD_CHECK(pool_.alloc(&st_normal_, 3 * cap));
+      VD_CHECK(pool_.alloc(&st_weight_, cap));
+      cap_dense_ = (int)cap;
+    }
+    if (S > cap_sparse_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(st_scanon_); pool_.release(st_starget_);
+      const size_t cap = (size_t)S + S / 4 + 16;
+      VD_CHECK(pool_.alloc(&st_scanon_, 3 * cap));
+      VD_CHECK(pool_.alloc(&st_starget_, 3 * cap));
+      cap_sparse_ = (int)cap;
+    }
+    return VD_OK;
+  }
+
+  int ensure_rows(int rows) {
+    if (rows > cap_rows_ || !keys_in_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      const int cap = rows + rows / 4 + 256;
+      pool_.release(keys_in_); pool_.release(keys_out_); pool_.release(vals_in_);
+      pool_.release(heads_); pool_.release(scan_); pool_.release(sort_temp_);
+      VD_CHECK(pool_.alloc(&keys_in_, cap));
+      VD_CHECK(pool_.alloc(&keys_out_, cap));
+      VD_CHECK(pool_.alloc(&vals_in_, cap));
+      VD_CHECK(pool_.alloc(&heads_, cap));
+      VD_CHECK(pool_.alloc(&scan_, cap));
+      sort_temp_bytes_ = std::max(vd::sort_temp_bytes(cap), vd::scan_temp_bytes(cap));
+      VD_CHECK(pool_.alloc((unsigned char**)&sort_temp_, sort_temp_bytes_));
+      cap_rows_ = cap;
+      ++alloc_gen_;
+    }
+    for (int l = 0; l < L_; ++l) {
+      LevelData<T>& v = lv_[l];
+      if (rows > v.cap_rows || !v.row_cell) {
+        const int cap = cap_rows_;
+        pool_.release(v.row_cell); pool_.release(v.sorted); pool_.release(v.row_f);
+        pool_.release(v.row_sn); pool_.release(v.row_rho);
+        VD_CHECK(pool_.alloc(&v.row_cell, cap));
+        VD_CHECK(pool_.alloc(&v.sorted, cap));
+        VD_CHECK(pool_.alloc(&v.row_f, 3 * (size_t)cap));
+        VD_CHECK(pool_.alloc(&v.row_sn, 3 * (size_t)cap));
+        VD_CHECK(pool_.alloc(&v.row_rho, cap));
+        v.cap_rows = cap;
+        ++alloc_gen_;
+      }
+      const int cells = std::max(1, std::min(v.ncell, v.cap_rows));
+      if (cells > v.cap_cells || !v.K) {
+        pool_.release(v.K); pool_.release(v.bcell); pool_.release(v.seg_start);
+        pool_.release(v.active_cell);
+        VD_CHECK(pool_.alloc(&v.K, (size_t)cells * 384));
+        VD_CHECK(pool_.alloc(&v.bcell, (size_t)cells * 24));
+        VD_CHECK(pool_.alloc(&v.seg_start, (size_t)cells + 1));
+        VD_CHECK(pool_.alloc(&v.active_cell, (size_t)cells));
+        v.cap_cells = cells;
+        ++alloc_gen_;
+      }
+      VD_CHECK(ensure_partials(v, v.cap_rows));
+    }
+    return VD_OK;
+  }
+
+  int ensure_debug() {
+    if (dbg_f_) return VD_OK;
+    const size_t N = finest().N;
+    VD_CHECK(pool_.alloc(&dbg_f_, 12 * N));
+    VD_CHECK(pool_.alloc(&dbg_t1_, 9 * N));
+    VD_CHECK(pool_.alloc(&dbg_t2_, 9 * N));
+    VD_CHECK(pool_.alloc(&dbg_rot_, 9 * N));
+    return VD_OK;
+  }
+
+  int upload_aos(const float* src, size_t n, int mem) {
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    VD_TRY(hipMemcpyAsync(dbg_f_, src, n * sizeof(float),
+                          mem == VD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                          stream_));
+    return VD_OK;
+  }
+
+  int download_aos(float* dst, size_t n, int mem) {
+    VD_TRY(hipMemcpyAsync(dst, dbg_f_, n * sizeof(float),
+                          mem == VD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                          stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  // A view of `level` whose d / rot are scratch copies of (pos - rest, rot).
+  int scratch_view(int level, const float* pos, const float* rot, int mem, LevelView<T>* out) {
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    VD_CHECK(ensure_debug());
+    LevelData<T>& v = lv_[level];
+    const size_t N = v.N;
+    const hipMemcpyKind kind = mem == VD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    VD_TRY(hipMemcpyAsync(dbg_f_, pos, 12 * N, kind, stream_));
+    VD_TRY(hipMemcpyAsync(dbg_f_ + 3 * N, rot, 36 * N, kind, stream_));
+    LevelView<T> V = v.view(desc_.w_arap);
+    V.d = dbg_t1_;
+    V.rot = dbg_rot_;
+    VD_TRY(launch_state_io<T>(V, desc_.origin, nullptr, nullptr, dbg_f_, dbg_f_ + 3 * N, 1,
+                              d_flags_, stream_));
+    *out = V;
+    return VD_OK;
+  }
+
+  vd_lattice_desc desc_;
+  hipStream_t stream_;
+  hipStream_t capture_stream_ = nullptr;
+  hipGraphExec_t graph_exec_[2] = {nullptr, nullptr};
+  long graph_gen_[2] = {-1, -1};
+  long alloc_gen_ = 0;
+  int L_ = 0;
+  std::vector<LevelData<T>> lv_;
+  Pool pool_;
+  int* d_flags_ = nullptr;
+  int* h_flags_ = nullptr;
+  Scalars* h_sc_ = nullptr;
+  // staging of the raw constraints
+  float *st_canon_ = nullptr, *st_target_ = nullptr, *st_normal_ = nullptr, *st_weight_ = nullptr,
+        *st_scanon_ = nullptr, *st_starget_ = nullptr;
+  int cap_dense_ = 0, cap_sparse_ = 0;
+  // sort scratch
+  unsigned *keys_in_ = nullptr, *keys_out_ = nullptr;
+  int *vals_in_ = nullptr, *heads_ = nullptr, *scan_ = nullptr;
+  void* sort_temp_ = nullptr;
+  size_t sort_temp_bytes_ = 0;
+  int cap_rows_ = 0;
+  int rows_ = 0, n_dense_ = 0;
+  bool have_constraints_ = false;
+  bool energy_fresh_ = false;
+  // test scratch
+  float* dbg_f_ = nullptr;
+  T *dbg_t1_ = nullptr, *dbg_t2_ = nullptr, *dbg_rot_ = nullptr;
+};
+
+}  // namespace vd
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+struct vd_lattice {
+  vd::ISolver* impl;
+};
+
+extern "C" {
+
+int vd_lattice_create(const vd_lattice_desc* d, void* stream, vd_lattice** out) {
+  if (!d || !out) return VD_EINVAL;
+  *out = nullptr;
+  if (d->num_levels < 1 || d->num_levels > VD_MAX_LEVELS) return VD_EINVAL;
+  if (!(d->spacing > 0) || !std::isfinite(d->spacing)) return VD_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    if (d->dims[k] < 2 || !std::isfinite(d->origin[k])) return VD_EINVAL;
+  }
+  if (!(d->w_dense >= 0) || !(d->w_sparse >= 0) || !(d->w_arap >= 0) ||
+      !std::isfinite(d->w_dense) || !std::isfinite(d->w_sparse) || !std::isfinite(d->w_arap))
+    return VD_EINVAL;
+  for (int l = 0; l < d->num_levels; ++l)
+    if (d->gn_iters[l] < 0 || d->pcg_iters[l] < 0) return VD_EINVAL;
+  {
+    int dims[3] = {d->dims[0], d->dims[1], d->dims[2]};
+    for (int l = 1; l < d->num_levels; ++l)
+      for (int k = 0; k < 3; ++k) dims[k] = (dims[k] + 1) / 2;
+    for (int k = 0; k < 3; ++k)
+      if (dims[k] < 2) return VD_EINVAL;
+  }
+  if (d->precision != VD_FP32_FP64RED && d->precision != VD_FP64) return VD_EINVAL;
+  vd::ISolver* impl = nullptr;
+  if (d->precision == VD_FP64)
+    impl = new (std::nothrow) vd::Solver<double>(*d, (hipStream_t)stream);
+  else
+    impl = new (std::nothrow) vd::Solver<float>(*d, (hipStream_t)stream);
+  if (!impl) return VD_ENOMEM;
+  const int rc = impl->init();
+  if (rc != VD_OK) {
+    delete impl;
+    return rc;
+  }
+  vd_lattice* h = new (std::nothrow) vd_lattice;
+  if (!h) {
+    delete impl;
+    return VD_ENOMEM;
+  }
+  h->impl = impl;
+  *out = h;
+  return VD_OK;
+}
+
+int vd_lattice_destroy(vd_lattice* l) {
+  if (!l) return VD_OK;
+  delete l->impl;
+  delete l;
+  return VD_OK;
+}
+
+int vd_set_constraints(vd_lattice* l, const vd_constraints* c) {
+  if (!l) return VD_EINVAL;
+  return l->impl->set_constraints(c);
+}
+
+int vd_solve_frame(vd_lattice* l, const vd_solve_opts* o, vd_solve_report* r) {
+  if (!l) return VD_EINVAL;
+  return l->impl->solve_frame(o, r);
+}
+
+int vd_get_energy(vd_lattice* l, double out[4]) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_energy(out);
+}
+
+int vd_get_state(vd_lattice* l, float* pos, float* rot, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_state(pos, rot, mem);
+}
+
+int vd_set_state(vd_lattice* l, const float* pos, const float* rot, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->set_state(pos, rot, mem);
+}
+
+int vd_level_info(const vd_lattice* l, int32_t level, int32_t dims[3], double* spacing) {
+  if (!l) return VD_EINVAL;
+  return l->impl->level_info(level, dims, spacing);
+}
+
+const char* vd_strerror(int code) {
+  switch (code) {
+    case VD_OK: return "ok";
+    case VD_EINVAL: return "invalid argument or non-finite / negative input";
+    case VD_ERANGE: return "a canonical sample lies outside the coarsest lattice";
+    case VD_ENOMEM: return "device allocation failed";
+    case VD_EHIP: return "HIP runtime error";
+    case VD_ESTATE: return "call not valid in the current state (no constraints set?)";
+    default: return "unknown status code";
+  }
+}
+
+int vd_debug_apply(vd_lattice* l, int32_t level, const float* p, float* Ap, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_apply(level, p, Ap, mem);
+}
+
+int vd_debug_gradient(vd_lattice* l, int32_t level, const float* pos, const float* rot, float* g,
+                      int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_gradient(level, pos, rot, g, mem);
+}
+
+int vd_debug_energy(vd_lattice* l, int32_t level, const float* pos, const float* rot,
+                    double out[4], int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_energy(level, pos, rot, out, mem);
+}
+
+int vd_debug_diag(vd_lattice* l, int32_t level, float* diag, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_diag(level, diag, mem);
+}
+
+int vd_debug_rotations(vd_lattice* l, int32_t level, const float* pos, const float* rot_prev,
+                       float* rot_out, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_rotations(level, pos, rot_prev, rot_out, mem);
+}
+
+int vd_debug_prolong(vd_lattice* l, int32_t level, const float* coarse, float* out, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_prolong(level, coarse, out, mem);
+}
+
+int vd_debug_fit_rotations(const float* M, const float* R_prev, float* R, int32_t* keep,
+                           int64_t n, int32_t precision, int32_t mem, void* stream) {
+  if (n < 0 || (n > 0 && (!M || !R))) return VD_EINVAL;
+  if (precision != VD_FP32_FP64RED && precision != VD_FP64) return VD_EINVAL;
+  if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+  if (n == 0) return VD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  float *dM = (float*)M, *dRp = (float*)R_prev, *dR = R;
+  int* dk = keep;
+  void* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto cleanup = [&]() {
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+  };
+  if (mem == VD_MEM_HOST) {
+    if (hipMalloc(&bufs[0], 36 * n) != hipSuccess || hipMalloc(&bufs[1], 36 * n) != hipSuccess ||
+        hipMalloc(&bufs[2], 36 * n) != hipSuccess || hipMalloc(&bufs[3], 4 * n) != hipSuccess) {
+      cleanup();
+      return VD_ENOMEM;
+    }
+    dM = (float*)bufs[0];
+    dRp = R_prev ? (float*)bufs[1] : nullptr;
+    dR = (float*)bufs[2];
+    dk = keep ? (int*)bufs[3] : nullptr;
+    if (hipMemcpyAsync(dM, M, 36 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (R_prev && hipMemcpyAsync(dRp, R_prev, 36 * n, hipMemcpyHostToDevice, s) != hipSuccess)) {
+      cleanup();
+      return VD_EHIP;
+    }
+  }
+  hipError_t e = precision == VD_FP64 ? vd::launch_fit_batch<double>(dM, dRp, dR, dk, n, s)
+                                      : vd::launch_fit_batch<float>(dM, dRp, dR, dk, n, s);
+  if (e == hipSuccess && mem == VD_MEM_HOST) {
+    e = hipMemcpyAsync(R, dR, 36 * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && keep) e = hipMemcpyAsync(keep, dk, 4 * n, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  return e == hipSuccess ? VD_OK : VD_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,1003 @@
+// HIP kernels of the lattice solver (gfx950).
+//
+// Unknowns are stored as displacements d_i = t_i - t_hat_i (float32 by
+// default): the residuals of eqs. (2)-(4) are then differences of small
+// numbers, which keeps float32 accurate even when the lattice sits far from
+// the world origin.  Every node vector is SoA [3][N] in x-fastest node order.
+
+#include "vd_device.h"
+#include "vd_kernels.h"
+
+namespace vd {
+
+namespace {
+
+inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ bool in_box(int x, int y, int z, int nx, int ny, int nz) {
+  return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+}
+
+// Row-major index of rotation entry (row, col) in the [9][N] SoA array.
+__device__ __forceinline__ size_t rot_at(int row, int col, size_t N, size_t i) {
+  return (size_t)(row * 3 + col) * N + i;
+}
+
+// Unique (a <= b) corner pairs of a cell and the six components of a
+// symmetric 3x3 block.
+__constant__ unsigned char c_pair_a[36] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2,
+                                           2, 2, 2, 3, 3, 3, 3, 3, 4, 4, 4, 4, 5, 5, 5, 6, 6, 7};
+__constant__ unsigned char c_pair_b[36] = {0, 1, 2, 3, 4, 5, 6, 7, 1, 2, 3, 4, 5, 6, 7, 2, 3, 4,
+                                           5, 6, 7, 3, 4, 5, 6, 7, 4, 5, 6, 7, 5, 6, 7, 6, 7, 7};
+__constant__ unsigned char c_comp_i[6] = {0, 0, 0, 1, 1, 2};
+__constant__ unsigned char c_comp_j[6] = {0, 1, 2, 1, 2, 2};
+
+}  // namespace
+
+// ===========================================================================
+// constraint validation and per-level rows
+// ===========================================================================
+
+__global__ __launch_bounds__(kBlock) void k_validate(RawConstraints c, int nx0, int ny0, int nz0,
+                                                     double h0, double ox, double oy, double oz,
+                                                     int* flags) {
+  const int total = c.n_dense + c.n_sparse;
+  int f = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    const float* pc;
+    const float* pt;
+    if (i < c.n_dense) {
+      pc = c.canon + 3 * (size_t)i;
+      pt = c.target + 3 * (size_t)i;
+      const float* pn = c.normal + 3 * (size_t)i;
+      for (int k = 0; k < 3; ++k)
+        if (!isfinite(pn[k])) f |= 1;
+      if (c.weight) {
+        const float w = c.weight[i];
+        if (!isfinite(w) || w < 0.0f) f |= 1;
+      }
+    } else {
+      const int s = i - c.n_dense;
+      pc = c.sparse_canon + 3 * (size_t)s;
+      pt = c.sparse_target + 3 * (size_t)s;
+    }
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(pc[k]) || !isfinite(pt[k])) f |= 1;
+    const double o[3] = {ox, oy, oz};
+    const int n[3] = {nx0, ny0, nz0};
+    for (int k = 0; k < 3; ++k) {
+      const double u = ((double)pc[k] - o[k]) / h0;
+      if (!(u >= 0.0 && u <= (double)(n[k] - 1))) f |= 2;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_validate(const RawConstraints& c, int nx0, int ny0, int nz0, double h0,
+                           const double* o, int* flags, hipStream_t s) {
+  const int total = c.n_dense + c.n_sparse;
+  if (total == 0) return hipSuccess;
+  int grid = blocks_for(total);
+  if (grid > 4096) grid = 4096;
+  k_validate<<<grid, kBlock, 0, s>>>(c, nx0, ny0, nz0, h0, o[0], o[1], o[2], flags);
+  return hipGetLastError();
+}
+
+// One row per dense correspondence (eq. (2)) and three per sparse pair
+// (eq. (3): a point-to-point term is the sum of three axis-aligned
+// point-to-plane terms).  Row value: sn . sum_k alpha_k d_k - rho, with
+// sn = sqrt(w) * normal and rho = sn . (target - canonical).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rows(RawConstraints c, LevelView<T> L, RowView<T> R,
+                                                 double ox, double oy, double oz, double wd,
+                                                 double ws, unsigned* keys, int* vals) {
+  const int rows = R.rows;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock) {
+    double x[3], sn[3], rho;
+    if (i < c.n_dense) {
+      const size_t b = 3 * (size_t)i;
+      double n[3], tp[3];
+      for (int k = 0; k < 3; ++k) {
+        x[k] = c.canon[b + k];
+        tp[k] = c.target[b + k];
+        n[k] = c.normal[b + k];
+      }
+      const double ln = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      double w = c.weight ? (double)c.weight[i] : 1.0;
+      if (ln > 0.0) {
+        for (int k = 0; k < 3; ++k) n[k] /= ln;
+      } else {
+        w = 0.0;
+        n[0] = n[1] = n[2] = 0.0;
+      }
+      const double s = sqrt(wd * w);
+      rho = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        sn[k] = s * n[k];
+        rho += sn[k] * (tp[k] - x[k]);
+      }
+    } else {
+      const int j = i - c.n_dense;
+      const int sidx = j / 3, axis = j % 3;
+      const size_t b = 3 * (size_t)sidx;
+      for (int k = 0; k < 3; ++k) x[k] = c.sparse_canon[b + k];
+      const double s = sqrt(ws);
+      sn[0] = sn[1] = sn[2] = 0.0;
+      sn[axis] = s;
+      rho = s * ((double)c.sparse_target[b + axis] - x[axis]);
+    }
+    const double o[3] = {ox, oy, oz};
+    const int n[3] = {L.nx, L.ny, L.nz};
+    int cc[3];
+    for (int k = 0; k < 3; ++k) {
+      const double u = (x[k] - o[k]) / (double)L.h;
+      double fl = floor(u);
+      if (fl < 0.0) fl = 0.0;
+      if (fl > (double)(n[k] - 2)) fl = (double)(n[k] - 2);
+      cc[k] = (int)fl;
+      R.f[(size_t)k * rows + i] = (T)(u - fl);
+      R.sn[(size_t)k * rows + i] = (T)sn[k];
+    }
+    const int cell = cc[0] + (L.nx - 1) * (cc[1] + (L.ny - 1) * cc[2]);
+    R.cell[i] = cell;
+    R.rho[i] = (T)rho;
+    keys[i] = (unsigned)cell;
+    vals[i] = i;
+  }
+}
+
+template <typename T>
+hipError_t launch_rows(const RawConstraints& c, const LevelView<T>& L, const RowView<T>& R,
+                       const double* o, double wd, double ws, unsigned* keys, int* vals,
+                       hipStream_t s) {
+  if (R.rows == 0) return hipSuccess;
+  int grid = blocks_for(R.rows);
+  if (grid > 4096) grid = 4096;
+  k_rows<T><<<grid, kBlock, 0, s>>>(c, L, R, o[0], o[1], o[2], wd, ws, keys, vals);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_heads(const unsigned* skeys, int n, int* heads) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    heads[i] = (i == 0 || skeys[i] != skeys[i - 1]) ? 1 : 0;
+}
+
+hipError_t launch_heads(const unsigned* skeys, int n, int* heads, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  k_heads<<<grid, kBlock, 0, s>>>(skeys, n, heads);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_int(int* p, int v, int n) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
+}
+
+// Active cells = distinct keys of the sorted rows.  `scan` is the exclusive
+// prefix sum of the head flags, i.e. the active index of each head.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_segments(RowView<T> R, const unsigned* skeys,
+                                                     const int* scan, int* cell_map, Scalars* sc) {
+  const int n = R.rows;
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->n_active = 0;
+      R.seg_start[0] = 0;
+    }
+    return;
+  }
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const bool head = (i == 0 || skeys[i] != skeys[i - 1]);
+    if (head) {
+      const int a = scan[i];
+      R.seg_start[a] = i;
+      R.active_cell[a] = (int)skeys[i];
+      cell_map[skeys[i]] = a;
+    }
+    if (i == n - 1) {
+      const int total = scan[i] + (head ? 1 : 0);
+      R.seg_start[total] = n;
+      sc->n_active = total;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_segments(const LevelView<T>& L, const RowView<T>& R, const unsigned* skeys,
+                           const int* scan, int* cell_map_w, int ncell, hipStream_t s) {
+  int g = blocks_for(ncell);
+  if (g > 4096) g = 4096;
+  k_fill_int<<<g, kBlock, 0, s>>>(cell_map_w, -1, ncell);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int grid = blocks_for(R.rows > 0 ? R.rows : 1);
+  if (grid > 4096) grid = 4096;
+  k_segments<T><<<grid, kBlock, 0, s>>>(R, skeys, scan, cell_map_w, L.sc);
+  return hipGetLastError();
+}
+
+// B^T B and B^T b cached per active cell (Sec. 7.1: "pre-compute and cache").
+// Block for corners (a, b): sum over the cell's rows of
+// alpha_a alpha_b sn sn^T (symmetric 3x3); rhs block of corner a:
+// sum alpha_a sn rho.  One workgroup per cell, one output entry per thread,
+// rows visited in sorted order (deterministic, float64 accumulation).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_build_cells(RowView<T> R, T* K, const Scalars* sc) {
+  const int n_active = sc->n_active;
+  const int rows = R.rows;
+  const int j = threadIdx.x;
+  int ca = 0, cb = 0, ci = 0, cj = 0, kind = 2;
+  if (j < 216) {
+    const int p = j / 6, comp = j % 6;
+    ca = c_pair_a[p];
+    cb = c_pair_b[p];
+    ci = c_comp_i[comp];
+    cj = c_comp_j[comp];
+    kind = 0;
+  } else if (j < 240) {
+    ca = (j - 216) / 3;
+    ci = (j - 216) % 3;
+    kind = 1;
+  }
+  for (int a = blockIdx.x; a < n_active; a += gridDim.x) {
+    const int s0 = R.seg_start[a], s1 = R.seg_start[a + 1];
+    double acc = 0.0;
+    if (kind < 2) {
+      for (int s = s0; s < s1; ++s) {
+        const int row = R.sorted[s];
+        const T fx = R.f[row], fy = R.f[(size_t)rows + row], fz = R.f[2 * (size_t)rows + row];
+        const T sni = R.sn[(size_t)ci * rows + row];
+        const double wa = (double)corner_weight<T>(ca, fx, fy, fz);
+        if (kind == 0) {
+          const T snj = R.sn[(size_t)cj * rows + row];
+          const double wb = (double)corner_weight<T>(cb, fx, fy, fz);
+          acc += wa * wb * (double)sni * (double)snj;
+        } else {
+          acc += wa * (double)sni * (double)R.rho[row];
+        }
+      }
+      if (kind == 0) {
+        const int comp = j % 6;
+        K[((size_t)a * 64 + ca * 8 + cb) * 6 + comp] = (T)acc;
+        if (ca != cb) K[((size_t)a * 64 + cb * 8 + ca) * 6 + comp] = (T)acc;
+      } else {
+        R.bcell[((size_t)a * 8 + ca) * 3 + ci] = (T)acc;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_build_cells(const LevelView<T>& L, const RowView<T>& R, T* K, int grid,
+                              hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  k_build_cells<T><<<grid, kBlock, 0, s>>>(R, K, L.sc);
+  return hipGetLastError();
+}
+
+// Per node: Jacobi diagonal diag(A) = 2 w_r |N_i| + data diagonal, and the
+// data right-hand side b_i, both gathered from the adjacent cells.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const int nb = (x > 0) + (x < L.nx - 1) + (y > 0) + (y < L.ny - 1) + (z > 0) + (z < L.nz - 1);
+  T dg[3] = {T(2) * L.wr * T(nb), T(2) * L.wr * T(nb), T(2) * L.wr * T(nb)};
+  T b[3] = {0, 0, 0};
+  const int cnx = L.nx - 1, cny = L.ny - 1, cnz = L.nz - 1;
+  for (int a = 0; a < 8; ++a) {
+    const int cx = x - (a & 1), cy = y - ((a >> 1) & 1), cz = z - (a >> 2);
+    if (!in_box(cx, cy, cz, cnx, cny, cnz)) continue;
+    const int ci = L.cell_map[cx + cnx * (cy + cny * cz)];
+    if (ci < 0) continue;
+    const T* blk = L.K + ((size_t)ci * 64 + a * 8 + a) * 6;
+    dg[0] += blk[0];
+    dg[1] += blk[3];
+    dg[2] += blk[5];
+    const T* bc = R.bcell + ((size_t)ci * 8 + a) * 3;
+    b[0] += bc[0];
+    b[1] += bc[1];
+    b[2] += bc[2];
+  }
+  const size_t N = L.N;
+  for (int k = 0; k < 3; ++k) {
+    L.dinv[k * N + i] = dg[k] > T(0) ? T(1) / dg[k] : T(0);
+    L.bnode[k * N + i] = b[k];
+  }
+}
+
+template <typename T>
+hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hipStream_t s) {
+  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// the normal-equation stencil (Sec. 7.1): A p = J^T J p
+// ===========================================================================
+//
+// A p at node i = 2 w_r sum_{j in N_i} (p_i - p_j)                (ARAP part)
+//               + sum_{adjacent cells c, i = corner a of c}
+//                   sum_{corners b} K_c[a][b] p_{corner b}        (data part)
+//
+// One workgroup per 8x8x4 tile; the tile plus a one-node halo of p is staged
+// in LDS (all 27 stencil neighbours of a tile node are in it).
+//
+// kModePcg : p = D^-1 r + beta p_old (p = D^-1 r on the first iteration) is
+//            formed while staging, written to p_new, Ap written, and the last
+//            block turns sum p.Ap into alpha = rz / p^T A p.
+// kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
+//            gradient J^T r; r = -g is stored and rz = r^T D^-1 r reduced.
+// kModeApply / kModeGrad : A p or g written to `out` (test entry points).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __restrict__ pin,
+                                                    T* __restrict__ out,
+                                                    const T* __restrict__ p_old,
+                                                    T* __restrict__ p_new) {
+  __shared__ T sp[3][kHalo];
+  const int ntx = (L.nx + kTX - 1) / kTX, nty = (L.ny + kTY - 1) / kTY;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * kTX - 1, y0 = ty * kTY - 1, z0 = tz * kTZ - 1;
+  const size_t N = L.N;
+
+  T beta = T(0);
+  bool first = true;
+  if (MODE == kModePcg) {
+    first = (L.sc->beta_valid == 0);
+    beta = (T)L.sc->beta;
+  }
+  const T* src = (MODE == kModeRhs) ? L.d : pin;
+
+  for (int k = threadIdx.x; k < kHalo; k += kBlock) {
+    const int lx = k % kHX, ly = (k / kHX) % kHY, lz = k / (kHX * kHY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    T v0 = T(0), v1 = T(0), v2 = T(0);
+    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+      const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+      if (MODE == kModePcg) {
+        v0 = L.dinv[i] * L.r[i];
+        v1 = L.dinv[N + i] * L.r[N + i];
+        v2 = L.dinv[2 * N + i] * L.r[2 * N + i];
+        if (!first) {
+          v0 += beta * p_old[i];
+          v1 += beta * p_old[N + i];
+          v2 += beta * p_old[2 * N + i];
+        }
+        if (lx >= 1 && lx <= kTX && ly >= 1 && ly <= kTY && lz >= 1 && lz <= kTZ) {
+          p_new[i] = v0;
+          p_new[N + i] = v1;
+          p_new[2 * N + i] = v2;
+        }
+      } else {
+        v0 = src[i];
+        v1 = src[N + i];
+        v2 = src[2 * N + i];
+      }
+    }
+    sp[0][k] = v0;
+    sp[1][k] = v1;
+    sp[2][k] = v2;
+  }
+  __syncthreads();
+
+  const int lx = threadIdx.x % kTX + 1, ly = (threadIdx.x / kTX) % kTY + 1,
+            lz = threadIdx.x / (kTX * kTY) + 1;
+  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+  const bool valid = in_box(gx, gy, gz, L.nx, L.ny, L.nz);
+  const int c = lx + kHX * (ly + kHY * lz);
+  T o0 = T(0), o1 = T(0), o2 = T(0);
+  T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
+  size_t i = 0;
+  if (valid) {
+    i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    // ARAP Laplacian
+    T l0 = T(0), l1 = T(0), l2 = T(0);
+    const int off[3] = {1, kHX, kHX * kHY};
+    const int pos[3] = {gx, gy, gz};
+    const int lim[3] = {L.nx, L.ny, L.nz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (pos[ax] > 0) {
+        const int q = c - off[ax];
+        l0 += p0 - sp[0][q];
+        l1 += p1 - sp[1][q];
+        l2 += p2 - sp[2][q];
+      }
+      if (pos[ax] < lim[ax] - 1) {
+        const int q = c + off[ax];
+        l0 += p0 - sp[0][q];
+        l1 += p1 - sp[1][q];
+        l2 += p2 - sp[2][q];
+      }
+    }
+    const T w2 = T(2) * L.wr;
+    o0 = w2 * l0;
+    o1 = w2 * l1;
+    o2 = w2 * l2;
+    // data term from the cached cell blocks
+    const int cnx = L.nx - 1, cny = L.ny - 1, cnz = L.nz - 1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int dx = a & 1, dy = (a >> 1) & 1, dz = a >> 2;
+      const int cx = gx - dx, cy = gy - dy, cz = gz - dz;
+      if (!in_box(cx, cy, cz, cnx, cny, cnz)) continue;
+      const int ci = L.cell_map[cx + cnx * (cy + cny * cz)];
+      if (ci < 0) continue;
+      const T* kr = L.K + ((size_t)ci * 64 + a * 8) * 6;
+      const int cb0 = c - dx - kHX * (dy + kHY * dz);  // local index of the cell's corner 0
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int q = cb0 + (b & 1) + kHX * (((b >> 1) & 1) + kHY * (b >> 2));
+        sym3_madd<T>(kr + b * 6, sp[0][q], sp[1][q], sp[2][q], o0, o1, o2);
+      }
+    }
+  }
+
+  if (MODE == kModeApply) {
+    if (valid) {
+      out[i] = o0;
+      out[N + i] = o1;
+      out[2 * N + i] = o2;
+    }
+    return;
+  }
+  if (MODE == kModeRhs || MODE == kModeGrad) {
+    T g0 = T(0), g1 = T(0), g2 = T(0);
+    if (valid) {
+      // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
+      // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
+      T q0 = T(0), q1 = T(0), q2 = T(0);
+      const int pos[3] = {gx, gy, gz};
+      const int lim[3] = {L.nx, L.ny, L.nz};
+      const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const T ci0 = L.rot[rot_at(0, ax, N, i)], ci1 = L.rot[rot_at(1, ax, N, i)],
+                ci2 = L.rot[rot_at(2, ax, N, i)];
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          const int pj = pos[ax] + sgn;
+          if (pj < 0 || pj >= lim[ax]) continue;
+          const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+          const T cj0 = L.rot[rot_at(0, ax, N, j)], cj1 = L.rot[rot_at(1, ax, N, j)],
+                  cj2 = L.rot[rot_at(2, ax, N, j)];
+          const T s = -T(sgn) * L.h;
+          T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
+          if (ax == 0) u0 += T(2);
+          if (ax == 1) u1 += T(2);
+          if (ax == 2) u2 += T(2);
+          q0 += s * u0;
+          q1 += s * u1;
+          q2 += s * u2;
+        }
+      }
+      g0 = o0 - L.bnode[i] + L.wr * q0;
+      g1 = o1 - L.bnode[N + i] + L.wr * q1;
+      g2 = o2 - L.bnode[2 * N + i] + L.wr * q2;
+    }
+    if (MODE == kModeGrad) {
+      if (valid) {
+        out[i] = g0;
+        out[N + i] = g1;
+        out[2 * N + i] = g2;
+      }
+      return;
+    }
+    double part[1] = {0.0};
+    if (valid) {
+      const T r0 = -g0, r1 = -g1, r2 = -g2;
+      L.r[i] = r0;
+      L.r[N + i] = r1;
+      L.r[2 * N + i] = r2;
+      part[0] = (double)(r0 * L.dinv[i]) * (double)r0 + (double)(r1 * L.dinv[N + i]) * (double)r1 +
+                (double)(r2 * L.dinv[2 * N + i]) * (double)r2;
+    }
+    double tot[1];
+    if (last_block_total<1>(part, L.partials, L.counter, tot)) {
+      if (threadIdx.x == 0) {
+        L.sc->rz = tot[0];
+        L.sc->beta = 0.0;
+        L.sc->beta_valid = 0;
+      }
+    }
+    return;
+  }
+  // kModePcg
+  double part[1] = {0.0};
+  if (valid) {
+    L.ap[i] = o0;
+    L.ap[N + i] = o1;
+    L.ap[2 * N + i] = o2;
+    part[0] = (double)p0 * (double)o0 + (double)p1 * (double)o1 + (double)p2 * (double)o2;
+  }
+  double tot[1];
+  if (last_block_total<1>(part, L.partials, L.counter, tot)) {
+    if (threadIdx.x == 0) {
+      const double rz = L.sc->rz;
+      const double pap = tot[0];
+      L.sc->pap = pap;
+      if (pap > 0.0) {
+        L.sc->alpha = rz / pap;
+      } else {
+        L.sc->alpha = 0.0;
+        L.sc->guard_hits += 1;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
+                          T* p_new, hipStream_t s) {
+  const int ntx = (L.nx + kTX - 1) / kTX, nty = (L.ny + kTY - 1) / kTY,
+            ntz = (L.nz + kTZ - 1) / kTZ;
+  const int grid = ntx * nty * ntz;
+  switch (mode) {
+    case kModePcg:
+      k_stencil<T, kModePcg><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      break;
+    case kModeRhs:
+      k_stencil<T, kModeRhs><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      break;
+    case kModeApply:
+      k_stencil<T, kModeApply><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      break;
+    case kModeGrad:
+      k_stencil<T, kModeGrad><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// CG phase B: d += alpha p; r -= alpha A p; rz_new = r^T D^-1 r; beta
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(LevelView<T> L, const T* __restrict__ p) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const size_t N = L.N;
+  const T alpha = (T)L.sc->alpha;
+  double part[1] = {0.0};
+  if (i < L.N) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const size_t j = k * N + i;
+      L.d[j] += alpha * p[j];
+      const T rn = L.r[j] - alpha * L.ap[j];
+      L.r[j] = rn;
+      acc += (double)(rn * L.dinv[j]) * (double)rn;
+    }
+    part[0] = acc;
+  }
+  double tot[1];
+  if (last_block_total<1>(part, L.partials, L.counter, tot)) {
+    if (threadIdx.x == 0) {
+      const double rz_old = L.sc->rz;
+      L.sc->beta = rz_old > 0.0 ? tot[0] / rz_old : 0.0;
+      L.sc->rz = tot[0];
+      L.sc->beta_valid = 1;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_update(const LevelView<T>& L, const T* p_new, hipStream_t s) {
+  k_update<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, p_new);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// energy, eq. (1): rows (dense and sparse) and ARAP edges, float64 sums
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R, int row_blocks,
+                                                   int record_trace) {
+  double part[3] = {0.0, 0.0, 0.0};
+  const size_t N = L.N;
+  if ((int)blockIdx.x < row_blocks) {
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int rows = L.sc->rows;
+    if (row < rows) {
+      const int cell = R.cell[row];
+      const int cnx = L.nx - 1, cny = L.ny - 1;
+      const int cx = cell % cnx, cy = (cell / cnx) % cny, cz = cell / (cnx * cny);
+      const T fx = R.f[row], fy = R.f[(size_t)rows + row], fz = R.f[2 * (size_t)rows + row];
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const size_t m = (cx + (k & 1)) + (size_t)L.nx * ((cy + ((k >> 1) & 1)) +
+                                                          (size_t)L.ny * (cz + (k >> 2)));
+        const T w = corner_weight<T>(k, fx, fy, fz);
+        s0 += w * L.d[m];
+        s1 += w * L.d[N + m];
+        s2 += w * L.d[2 * N + m];
+      }
+      const T res = R.sn[row] * s0 + R.sn[(size_t)rows + row] * s1 +
+                    R.sn[2 * (size_t)rows + row] * s2 - R.rho[row];
+      const double e = (double)res * (double)res;
+      if (row < L.sc->n_dense) part[0] = e; else part[1] = e;
+    }
+  } else {
+    const int i = (blockIdx.x - row_blocks) * kBlock + threadIdx.x;
+    if (i < L.N) {
+      const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+      const int pos[3] = {x, y, z};
+      const int lim[3] = {L.nx, L.ny, L.nz};
+      const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+      double acc = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        // (I - R_i) e_ij with e_ij = -s h axis
+        T c0 = -L.rot[rot_at(0, ax, N, i)], c1 = -L.rot[rot_at(1, ax, N, i)],
+          c2 = -L.rot[rot_at(2, ax, N, i)];
+        if (ax == 0) c0 += T(1);
+        if (ax == 1) c1 += T(1);
+        if (ax == 2) c2 += T(1);
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          const int pj = pos[ax] + sgn;
+          if (pj < 0 || pj >= lim[ax]) continue;
+          const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+          const T s = -T(sgn) * L.h;
+          const T e0 = L.d[i] - L.d[j] + s * c0;
+          const T e1 = L.d[N + i] - L.d[N + j] + s * c1;
+          const T e2 = L.d[2 * N + i] - L.d[2 * N + j] + s * c2;
+          acc += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        }
+      }
+      part[2] = (double)L.wr * acc;
+    }
+  }
+  double tot[3];
+  if (last_block_total<3>(part, L.partials, L.counter, tot)) {
+    if (threadIdx.x == 0) {
+      Scalars* sc = L.sc;
+      sc->energy[0] = tot[0] + tot[1] + tot[2];
+      sc->energy[1] = tot[0];
+      sc->energy[2] = tot[1];
+      sc->energy[3] = tot[2];
+      if (record_trace && sc->n_trace < VD_MAX_TRACE) {
+        sc->trace[sc->n_trace] = sc->energy[0];
+        sc->n_trace += 1;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_energy(const LevelView<T>& L, const RowView<T>& R, int cap_rows,
+                         int record_trace, hipStream_t s) {
+  const int rb = blocks_for(cap_rows);
+  const int nb = blocks_for(L.N);
+  k_energy<T><<<rb + nb, kBlock, 0, s>>>(L, R, rb, record_trace);
+  return hipGetLastError();
+}
+
+__global__ void k_reset_counters(Scalars* sc, int rows, int n_dense, int clear_trace) {
+  if (threadIdx.x != 0) return;
+  sc->guard_hits = 0;
+  sc->polar_fp64 = 0;
+  sc->polar_keep = 0;
+  if (clear_trace) sc->n_trace = 0;
+  if (rows >= 0) sc->rows = rows;
+  if (n_dense >= 0) sc->n_dense = n_dense;
+}
+
+hipError_t launch_reset_counters(Scalars* sc, int rows, int n_dense, int clear_trace,
+                                 hipStream_t s) {
+  k_reset_counters<<<1, 64, 0, s>>>(sc, rows, n_dense, clear_trace);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finite(const float* v, int64_t n, int* flags) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    if (!isfinite(v[i])) bad = 1;
+  if (bad) atomicOr(flags, 1);
+}
+
+hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 4096) g = 4096;
+  k_check_finite<<<(unsigned)g, kBlock, 0, s>>>(v, n, flags);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// rotation step (Sec. 7.1): M_i = sum_j (t_i - t_j)(t_hat_i - t_hat_j)^T
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_polar(LevelView<T> L, const T* __restrict__ d,
+                                                  const T* rot_prev, T* rot_out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const int pos[3] = {x, y, z};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+  const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+  const T di0 = d[i], di1 = d[N + i], di2 = d[2 * N + i];
+  T M[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = T(0);
+  const T h2 = L.h * L.h;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const int pj = pos[ax] + sgn;
+      if (pj < 0 || pj >= lim[ax]) continue;
+      const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+      // (d_i - d_j + e_ij) e_ij^T with e_ij = -s h axis: column ax gets
+      // -s h (d_i - d_j) + h^2 axis
+      const T s = -T(sgn) * L.h;
+      M[0 * 3 + ax] += s * (di0 - d[j]);
+      M[1 * 3 + ax] += s * (di1 - d[N + j]);
+      M[2 * 3 + ax] += s * (di2 - d[2 * N + j]);
+      M[ax * 3 + ax] += h2;
+    }
+  }
+  T Rp[9], R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rp[k] = rot_prev[(size_t)k * N + i];
+  const int code = fit_or_keep<T>(M, Rp, R);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) rot_out[(size_t)k * N + i] = R[k];
+  if (code == kFitFp64) atomicAdd(&L.sc->polar_fp64, 1);
+  if (code == kFitKeep) atomicAdd(&L.sc->polar_keep, 1);
+}
+
+template <typename T>
+hipError_t launch_polar(const LevelView<T>& L, const T* d_in, const T* rot_prev, T* rot_out,
+                        hipStream_t s) {
+  k_polar<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, d_in, rot_prev, rot_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fit_batch(const float* M, const float* Rp, float* R,
+                                                      int* keep, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T m[9], rp[9], r[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    m[k] = (T)M[9 * i + k];
+    rp[k] = Rp ? (T)Rp[9 * i + k] : ((k % 4 == 0) ? T(1) : T(0));
+  }
+  const int code = fit_or_keep<T>(m, rp, r);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[9 * i + k] = (float)r[k];
+  if (keep) keep[i] = code;
+}
+
+template <typename T>
+hipError_t launch_fit_batch(const float* M, const float* R_prev, float* R, int* keep, int64_t n,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_fit_batch<T><<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(M, R_prev, R, keep, n);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// level transfers (Sec. 7.2)
+// ===========================================================================
+
+// Level node (a,b,c) takes the finest node stride*(a,b,c): d, base and R.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_inject(LevelView<T> F, LevelView<T> Lv, int stride) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= Lv.N) return;
+  const int x = i % Lv.nx, y = (i / Lv.nx) % Lv.ny, z = i / (Lv.nx * Lv.ny);
+  const size_t f = (size_t)x * stride + (size_t)F.nx * ((size_t)y * stride + (size_t)F.ny * z * stride);
+  const size_t N = Lv.N, NF = F.N;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T v = F.d[k * NF + f];
+    Lv.d[k * N + i] = v;
+    Lv.base[k * N + i] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Lv.rot[k * N + i] = F.rot[k * NF + f];
+}
+
+template <typename T>
+hipError_t launch_inject(const LevelView<T>& fine, const LevelView<T>& lvl, int stride,
+                         hipStream_t s) {
+  k_inject<T><<<blocks_for(lvl.N), kBlock, 0, s>>>(fine, lvl, stride);
+  return hipGetLastError();
+}
+
+// fine_out (+)= trilinear evaluation of (coarse_in - coarse_base) at the fine
+// rest positions: fine node a sits at coarse coordinate a/2; its cell is
+// clamped to the last coarse cell, so the last fine plane of an even-sized
+// axis is linearly extrapolated (f = 1.5).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> C, LevelView<T> Fl,
+                                                    const T* __restrict__ cin,
+                                                    const T* __restrict__ cbase, T* fout,
+                                                    int add) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= Fl.N) return;
+  const int x = i % Fl.nx, y = (i / Fl.nx) % Fl.ny, z = i / (Fl.nx * Fl.ny);
+  const int p[3] = {x, y, z};
+  const int nc[3] = {C.nx, C.ny, C.nz};
+  int cc[3];
+  T f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int c = p[k] >> 1;
+    if (c > nc[k] - 2) c = nc[k] - 2;
+    cc[k] = c;
+    f[k] = T(0.5) * T(p[k]) - T(c);
+  }
+  const size_t NC = C.N, NF = Fl.N;
+  T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const size_t m = (cc[0] + (k & 1)) +
+                     (size_t)C.nx * ((cc[1] + ((k >> 1) & 1)) + (size_t)C.ny * (cc[2] + (k >> 2)));
+    const T w = corner_weight<T>(k, f[0], f[1], f[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T inc = cbase ? cin[a * NC + m] - cbase[a * NC + m] : cin[a * NC + m];
+      v[a] += w * inc;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (add) fout[a * NF + i] += v[a];
+    else fout[a * NF + i] = v[a];
+  }
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const LevelView<T>& coarse, const LevelView<T>& fine,
+                              const T* coarse_in, const T* coarse_base, T* fine_out, int add,
+                              hipStream_t s) {
+  k_prolong<T><<<blocks_for(fine.N), kBlock, 0, s>>>(coarse, fine, coarse_in, coarse_base,
+                                                      fine_out, add);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// state helpers
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set_rest(LevelView<T> L) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) L.d[k * N + i] = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) L.rot[k * N + i] = (k % 4 == 0) ? T(1) : T(0);
+}
+
+template <typename T>
+hipError_t launch_set_rest(const LevelView<T>& L, hipStream_t s) {
+  k_set_rest<T><<<blocks_for(L.N), kBlock, 0, s>>>(L);
+  return hipGetLastError();
+}
+
+// dir 0: export positions t = t_hat + d (AoS float) and rotations (row-major
+// AoS float); dir 1: import them (non-finite input sets flags bit 1).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_state_io(LevelView<T> L, double ox, double oy,
+                                                     double oz, float* pos, float* rot,
+                                                     const float* pos_in, const float* rot_in,
+                                                     int dir, int* flags) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const double rest[3] = {ox + (double)L.h * x, oy + (double)L.h * y, oz + (double)L.h * z};
+  if (dir == 0) {
+    if (pos) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pos[3 * (size_t)i + k] = (float)(rest[k] + (double)L.d[k * N + i]);
+    }
+    if (rot) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) rot[9 * (size_t)i + k] = (float)L.rot[k * N + i];
+    }
+  } else {
+    int bad = 0;
+    if (pos_in) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float v = pos_in[3 * (size_t)i + k];
+        if (!isfinite(v)) bad = 1;
+        L.d[k * N + i] = (T)((double)v - rest[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float v = rot_in ? rot_in[9 * (size_t)i + k] : ((k % 4 == 0) ? 1.0f : 0.0f);
+      if (!isfinite(v)) bad = 1;
+      L.rot[k * N + i] = (T)v;
+    }
+    if (bad) atomicOr(flags, 1);
+  }
+}
+
+template <typename T>
+hipError_t launch_state_io(const LevelView<T>& L, const double* o, float* pos, float* rot,
+                           const float* pos_in, const float* rot_in, int dir, int* flags,
+                           hipStream_t s) {
+  k_state_io<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, o[0], o[1], o[2], pos, rot, pos_in, rot_in,
+                                                    dir, flags);
+  return hipGetLastError();
+}
+
+// AoS float xyz <-> SoA T (used by the test entry points)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_convert(const float* in, T* out, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[(size_t)k * n + i] = (T)in[3 * (size_t)i + k];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_convert_back(const T* in, float* out, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[3 * (size_t)i + k] = (float)in[(size_t)k * n + i];
+}
+template <typename T>
+hipError_t launch_convert(const float* in, T* out, int n, hipStream_t s) {
+  k_convert<T><<<blocks_for(n), kBlock, 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
+  k_convert_back<T><<<blocks_for(n), kBlock, 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+
+// ---- explicit instantiations -----------------------------------------------
+#define VD_INSTANTIATE(T)                                                                        \
+  template hipError_t launch_rows<T>(const RawConstraints&, const LevelView<T>&,                \
+                                     const RowView<T>&, const double*, double, double,          \
+                                     unsigned*, int*, hipStream_t);                             \
+  template hipError_t launch_segments<T>(const LevelView<T>&, const RowView<T>&,                \
+                                         const unsigned*, const int*, int*, int, hipStream_t);  \
+  template hipError_t launch_build_cells<T>(const LevelView<T>&, const RowView<T>&, T*, int,    \
+                                            hipStream_t);                                       \
+  template hipError_t launch_assemble_nodes<T>(const LevelView<T>&, const RowView<T>&,          \
+                                               hipStream_t);                                    \
+  template hipError_t launch_stencil<T>(int, const LevelView<T>&, const T*, T*, T*, T*,         \
+                                        hipStream_t);                                           \
+  template hipError_t launch_update<T>(const LevelView<T>&, const T*, hipStream_t);             \
+  template hipError_t launch_energy<T>(const LevelView<T>&, const RowView<T>&, int, int,        \
+                                       hipStream_t);                                            \
+  template hipError_t launch_polar<T>(const LevelView<T>&, const T*, const T*, T*, hipStream_t); \
+  template hipError_t launch_inject<T>(const LevelView<T>&, const LevelView<T>&, int,           \
+                                       hipStream_t);                                            \
+  template hipError_t launch_prolong_add<T>(const LevelView<T>&, const LevelView<T>&,           \
+                                            const T*, const T*, T*, int, hipStream_t);          \
+  template hipError_t launch_set_rest<T>(const LevelView<T>&, hipStream_t);                     \
+  template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \
+                                         const float*, const float*, int, int*, hipStream_t);   \
+  template hipError_t launch_convert<T>(const float*, T*, int, hipStream_t);                    \
+  template hipError_t launch_convert_back<T>(const T*, float*, int, hipStream_t);               \
+  template hipError_t launch_fit_batch<T>(const float*, const float*, float*, int*, int64_t,    \
+                                          hipStream_t);
+
+VD_INSTANTIATE(float)
+VD_INSTANTIATE(double)
+
+}  // namespace vd

@@ -1,0 +1,163 @@
+// Kernel launchers of the lattice solver.  Everything is templated on the
+// node-vector type T (float for VD_FP32_FP64RED, double for VD_FP64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vd.h"
+
+namespace vd {
+
+// Device-resident scalars of one level.  Written only by the last block of a
+// reduction kernel (or by a single thread), read by the next kernel.
+struct Scalars {
+  double rz;      // r^T D^-1 r of the current CG iterate
+  double pap;     // p^T A p
+  double alpha;   // CG step size
+  double beta;    // CG direction update
+  double energy[4];
+  int beta_valid;  // 0 right after the gradient pass: p = z on the next phase A
+  int guard_hits;  // zero-denominator guards taken
+  int polar_fp64;  // rotation fits redone in float64
+  int polar_keep;  // degenerate rotation fits (previous R kept)
+  int n_active;    // cells holding at least one constraint row
+  int n_trace;
+  int rows;        // constraint rows of the current frame (dense + 3 sparse)
+  int n_dense;     // dense rows among them
+  double trace[VD_MAX_TRACE];
+};
+
+// Per-level view passed to kernels by value.
+template <typename T>
+struct LevelView {
+  int nx, ny, nz;
+  int N;            // nx * ny * nz
+  T h;              // node spacing of this level
+  T wr;             // w_arap
+  // node vectors, SoA [3][N] (rot: [9][N], row-major entries)
+  T* d;       // displacement t - t_hat (the unknowns)
+  T* r;       // CG residual (= -gradient after the gradient pass)
+  T* ap;      // A p
+  T* dinv;    // Jacobi preconditioner 1 / diag(A)
+  T* bnode;   // J^T (weighted targets) of the data rows, per node
+  T* base;    // finest state injected to this level (for the increment)
+  T* rot;     // rotations
+  // constraint cache
+  const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
+  const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
+  Scalars* sc;
+  double* partials;
+  unsigned* counter;
+};
+
+// Constraint rows of one level (dense rows then 3 rows per sparse pair).
+template <typename T>
+struct RowView {
+  int rows;        // C + 3 S
+  int n_dense;     // C
+  int* cell;       // linear cell id per row
+  T* f;            // [3][rows] fractional coordinates
+  T* sn;           // [3][rows] sqrt(w) * normal
+  T* rho;          // [rows]    sqrt(w) * normal . (target - canonical)
+  int* sorted;     // rows ordered by cell
+  int* seg_start;  // [active + 1] start of each active cell's rows in `sorted`
+  T* bcell;        // [active][8][3] per-cell right-hand side blocks
+  int* active_cell;  // [active] linear cell id
+};
+
+struct RawConstraints {
+  const float* canon;
+  const float* target;
+  const float* normal;
+  const float* weight;  // may be null (all 1)
+  const float* sparse_canon;
+  const float* sparse_target;
+  int n_dense, n_sparse;
+};
+
+// ---- constraint build ----------------------------------------------------
+hipError_t launch_validate(const RawConstraints& c, int nx0, int ny0, int nz0, double h0,
+                           const double* origin, int* flags, hipStream_t s);
+
+template <typename T>
+hipError_t launch_rows(const RawConstraints& c, const LevelView<T>& L, const RowView<T>& R,
+                       const double* origin, double w_dense, double w_sparse,
+                       unsigned* keys, int* vals, hipStream_t s);
+
+template <typename T>
+hipError_t launch_segments(const LevelView<T>& L, const RowView<T>& R, const unsigned* skeys,
+                           const int* scan, int* cell_map_w, int ncell, hipStream_t s);
+
+hipError_t launch_heads(const unsigned* skeys, int n, int* heads, hipStream_t s);
+
+template <typename T>
+hipError_t launch_build_cells(const LevelView<T>& L, const RowView<T>& R, T* K, int grid,
+                              hipStream_t s);
+
+template <typename T>
+hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hipStream_t s);
+
+// ---- solve ---------------------------------------------------------------
+enum StencilMode { kModePcg = 0, kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
+
+template <typename T>
+hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
+                          T* p_new, hipStream_t s);
+
+template <typename T>
+hipError_t launch_update(const LevelView<T>& L, const T* p_new, hipStream_t s);
+
+// Energy over the rows (count read from sc->rows; grid sized by `cap_rows`)
+// and the ARAP edges of level L.
+template <typename T>
+hipError_t launch_energy(const LevelView<T>& L, const RowView<T>& R, int cap_rows,
+                         int record_trace, hipStream_t s);
+
+// Per-frame counters of a level back to zero; rows/n_dense stored when >= 0.
+hipError_t launch_reset_counters(Scalars* sc, int rows, int n_dense, int clear_trace,
+                                 hipStream_t s);
+
+// flags |= 1 where any of the n floats is not finite.
+hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s);
+
+template <typename T>
+hipError_t launch_polar(const LevelView<T>& L, const T* d_in, const T* rot_prev, T* rot_out,
+                        hipStream_t s);
+
+template <typename T>
+hipError_t launch_inject(const LevelView<T>& fine, const LevelView<T>& lvl, int stride,
+                         hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong_add(const LevelView<T>& coarse, const LevelView<T>& fine,
+                              const T* coarse_in, const T* coarse_base, T* fine_out, int add,
+                              hipStream_t s);
+
+template <typename T>
+hipError_t launch_set_rest(const LevelView<T>& L, hipStream_t s);
+
+template <typename T>
+hipError_t launch_state_io(const LevelView<T>& L, const double* origin, float* pos, float* rot,
+                           const float* pos_in, const float* rot_in, int dir, int* flags,
+                           hipStream_t s);
+
+template <typename T>
+hipError_t launch_convert(const float* in, T* out, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s);
+
+// Batched rotation fit of raw matrices (test entry point).
+template <typename T>
+hipError_t launch_fit_batch(const float* M, const float* R_prev, float* R, int* keep, int64_t n,
+                            hipStream_t s);
+
+// rocPRIM-backed primitives (separate translation unit).
+size_t sort_temp_bytes(int n);
+hipError_t sort_pairs(void* temp, size_t bytes, const unsigned* kin, unsigned* kout,
+                      const int* vin, int* vout, int n, int end_bit, hipStream_t s);
+size_t scan_temp_bytes(int n);
+hipError_t exclusive_scan(void* temp, size_t bytes, const int* in, int* out, int n,
+                          hipStream_t s);
+
+}  // namespace vd

@@ -1,0 +1,59 @@
+"""Shared helpers of the test suite: run the oracle and the GPU library on the
+same seeded scene and compare."""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from oracle.energy import prepare_constraints
+from oracle.lattice import level_grids
+
+
+def grids_of(scene):
+    s = scene.spec
+    return level_grids(s.dims, s.spacing, s.origin, s.num_levels)
+
+
+def oracle_cons(scene):
+    return prepare_constraints(scene, grids_of(scene)[0])
+
+
+def random_state(grid, rng, amp=0.3, rot_amp=0.3):
+    """Positions rest + amp*h*N(0,1) and rotations exp(rot_amp * N(0,1) axis)."""
+    pos = grid.rest_positions() + amp * grid.h * rng.normal(size=(grid.n, 3))
+    w = rot_amp * rng.normal(size=(grid.n, 3))
+    th = np.linalg.norm(w, axis=1, keepdims=True)
+    k = w / np.maximum(th, 1e-30)
+    K = np.zeros((grid.n, 3, 3))
+    K[:, 0, 1], K[:, 0, 2] = -k[:, 2], k[:, 1]
+    K[:, 1, 0], K[:, 1, 2] = k[:, 2], -k[:, 0]
+    K[:, 2, 0], K[:, 2, 1] = -k[:, 1], k[:, 0]
+    s, c = np.sin(th)[..., None], np.cos(th)[..., None]
+    R = np.eye(3)[None] + s * K + (1 - c) * (K @ K)
+    return pos.astype(np.float32), R.astype(np.float32)
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rotation_angle(Ra, Rb):
+    """Angle (rad) of Ra^T Rb per node."""
+    Ra = np.asarray(Ra, np.float64)
+    Rb = np.asarray(Rb, np.float64)
+    tr = np.einsum("nab,nab->n", Ra, Rb)
+    return np.arccos(np.clip((tr - 1.0) / 2.0, -1.0, 1.0))
+
+
+def make_lattice(scene, **kw):
+    from paper_1603_08161_amd import Lattice
+    lat = Lattice.from_spec(scene.spec, **kw)
+    lat.set_scene(scene)
+    return lat
+
+
+def oracle_solve(scene, **kw):
+    return oracle.solve_frame(scene, **kw)

@@ -1,0 +1,175 @@
+"""Frame-solve parity on the GPU: the whole flip-flop / CG / hierarchy
+schedule through vd_solve_frame against the oracle's replica mode (the same
+Jacobi-PCG algorithm and counts in float64).  Gates: final energy within
+1e-4 relative, node positions within 1e-3 of the finest spacing."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_config0, make_config1, make_tiny, random_rotation
+from synth.scenes import make_identity_scene, make_rigid_scene
+
+from helpers import grids_of, make_lattice, rel_err, rotation_angle
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_against_oracle(scene, lat_kw=None, e_tol=1e-4, x_tol=1e-3):
+    ref = oracle.solve_frame(scene)
+    lat = make_lattice(scene, **(lat_kw or {}))
+    rep = lat.solve_frame(report=True)
+    pos, rot = lat.get_state()
+    h = scene.spec.spacing
+    dx = np.abs(pos.astype(np.float64) - ref["t"]).max() / h
+    e_gpu, e_ref = rep["energy"], np.asarray(ref["energy"])
+    assert abs(e_gpu[0] / e_ref[0] - 1.0) < e_tol, (e_gpu, e_ref)
+    assert dx < x_tol, dx
+    assert rotation_angle(rot, ref["R"]).max() < 1e-2
+    np.testing.assert_allclose(lat.get_energy(), e_gpu, rtol=1e-12)
+    return lat, rep, ref
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cfg0_matches_replica(precision):
+    _check_against_oracle(make_config0(0), {"precision": precision})
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ragged_multilevel_matches_replica(seed):
+    scene = make_tiny(seed=seed, dims=(19, 14, 10), num_levels=3, gn=3, pcg=8, n_dense=800,
+                      n_sparse=30, spacing=0.7, origin=(0.5, -2.0, 1.0))
+    _check_against_oracle(scene)
+
+
+def test_cfg1_matches_replica():
+    """The 64^3, 3-level x 8 GN x 20 PCG frame the benchmark times."""
+    lat, rep, ref = _check_against_oracle(make_config1(0))
+    assert rep["bits"] & 1 == 0  # no CG guard hits on a well-posed frame
+
+
+def test_graph_replay_equals_eager():
+    scene = make_config0(1)
+    eager = make_lattice(scene)
+    graph = make_lattice(scene, graph=True)
+    for k in range(3):
+        e1 = eager.solve_frame(reset=True, report=True)["energy"]
+        e2 = graph.solve_frame(reset=True, report=True)["energy"]
+        np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(eager.get_state()[0], graph.get_state()[0])
+
+
+def test_deterministic_rerun_and_resume():
+    scene = make_config0(2)
+    a = make_lattice(scene)
+    a.solve_frame()
+    pos_a, rot_a = a.get_state()
+    a.solve_frame()
+    pos_a2, _ = a.get_state()
+    # resume from a checkpoint of the first frame in a fresh handle
+    b = make_lattice(scene)
+    b.set_state(pos_a, rot_a)
+    b.solve_frame()
+    np.testing.assert_array_equal(b.get_state()[0], pos_a2)
+    c = make_lattice(scene)
+    c.solve_frame()
+    np.testing.assert_array_equal(c.get_state()[0], pos_a)
+
+
+def test_trace_is_monotone():
+    scene = make_config0(3)
+    lat = make_lattice(scene, trace=True)
+    rep = lat.solve_frame(report=True)
+    tr = rep["trace"]
+    assert tr.size == 2 * scene.spec.gn_iters[0]
+    assert np.all(np.diff(tr) <= 1e-6 * tr[:-1])
+    trace_ref = []
+    oracle.solve_frame(scene, trace=trace_ref)
+    np.testing.assert_allclose(tr, [e for (_, _, e) in trace_ref], rtol=1e-4)
+
+
+@pytest.mark.parametrize("levels", [1, 3])
+def test_rigid_fixed_point(levels):
+    rng = np.random.default_rng(10 + levels)
+    base = make_tiny(seed=10 + levels, dims=(17, 12, 9), num_levels=levels, gn=2, pcg=6,
+                     n_dense=300, n_sparse=8)
+    Q = random_rotation(rng)
+    c = rng.normal(size=3)
+    scene = make_rigid_scene(base, Q, c)
+    fin = grids_of(scene)[-1]
+    t0 = (fin.rest_positions() @ Q.T + c).astype(np.float32)
+    R0 = np.broadcast_to(Q, (fin.n, 3, 3)).astype(np.float32)
+    lat = make_lattice(scene)
+    lat.set_state(t0, R0)
+    e0 = lat.get_energy()
+    lat.solve_frame()
+    pos, rot = lat.get_state()
+    assert np.abs(pos - t0).max() < 1e-4 * scene.spec.spacing * 10
+    assert rotation_angle(rot, R0).max() < 1e-4
+    assert lat.get_energy()[0] <= max(e0[0], 1e-9) * 1.01
+
+
+@pytest.mark.parametrize("levels", [1, 3])
+def test_identity_stays_at_rest(levels):
+    base = make_tiny(seed=20, dims=(9, 9, 9), num_levels=levels, n_dense=100)
+    scene = make_identity_scene(base)
+    lat = make_lattice(scene)
+    rep = lat.solve_frame(report=True)
+    pos, rot = lat.get_state()
+    rest = grids_of(scene)[-1].rest_positions()
+    assert np.all(np.isfinite(pos)) and np.all(np.isfinite(rot))
+    assert np.abs(pos - rest).max() < 1e-5
+    assert rotation_angle(rot, np.broadcast_to(np.eye(3), rot.shape)).max() < 1e-5
+    assert rep["energy"][0] < 1e-8
+
+
+def test_validation_errors_leave_handle_unchanged():
+    from paper_1603_08161_amd import VDError, VD_ERANGE, VD_EINVAL, VD_ESTATE
+    scene = make_config0(4)
+    from paper_1603_08161_amd import Lattice
+    lat = Lattice.from_spec(scene.spec)
+    with pytest.raises(VDError) as ei:
+        lat.solve_frame()
+    assert ei.value.code == VD_ESTATE
+    lat.set_scene(scene)
+    lat.solve_frame()
+    e_ok = lat.get_energy()
+    bad = scene.canon.copy()
+    bad[7] = [20.0, 1.0, 1.0]
+    with pytest.raises(VDError) as ei:
+        lat.set_constraints(bad, scene.target, scene.normal, scene.weight,
+                            scene.sparse_canon, scene.sparse_target)
+    assert ei.value.code == VD_ERANGE
+    nan = scene.target.copy()
+    nan[3, 1] = np.nan
+    with pytest.raises(VDError) as ei:
+        lat.set_constraints(scene.canon, nan, scene.normal)
+    assert ei.value.code == VD_EINVAL
+    neg = scene.weight.copy()
+    neg[0] = -1
+    with pytest.raises(VDError) as ei:
+        lat.set_constraints(scene.canon, scene.target, scene.normal, neg)
+    assert ei.value.code == VD_EINVAL
+    np.testing.assert_allclose(lat.get_energy(), e_ok, rtol=1e-12)
+
+
+def test_device_tensor_inputs_match_host():
+    import torch
+    scene = make_config0(5)
+    host = make_lattice(scene)
+    host.solve_frame()
+    dev = make_lattice(scene)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dev.set_constraints(t(scene.canon), t(scene.target), t(scene.normal), t(scene.weight),
+                        t(scene.sparse_canon), t(scene.sparse_target))
+    dev.solve_frame()
+    np.testing.assert_array_equal(host.get_state()[0], dev.get_state()[0])
+
+
+def test_empty_constraints():
+    base = make_tiny(seed=30, dims=(6, 5, 4), n_dense=0, n_sparse=0)
+    lat = make_lattice(base)
+    rep = lat.solve_frame(report=True)
+    pos, _ = lat.get_state()
+    np.testing.assert_allclose(pos, grids_of(base)[-1].rest_positions(), atol=1e-6)
+    assert rep["energy"][0] == 0.0
