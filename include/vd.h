@@ -65,6 +65,17 @@ extern "C" {
 #define VD_FLAG_GRAPH 1u /* capture each frame's schedule in a hipGraph and
                             replay it (default launch path when set) */
 #define VD_FLAG_TRACE 2u /* record E_total after every half-step */
+#define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events
+                              (ignored when VD_FLAG_GRAPH is set) */
+
+/* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
+#define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
+#define VD_PROF_CG_A 1      /* CG phase A: p update + A p stencil + p^T A p */
+#define VD_PROF_CG_B 2      /* CG phase B: d, r update + r^T D^-1 r */
+#define VD_PROF_ROTATION 3  /* rotation fits */
+#define VD_PROF_ENERGY 4    /* energy evaluation */
+#define VD_PROF_TRANSFER 5  /* injection / prolongation */
+#define VD_PROF_KINDS 8
 
 /* ---- report bits -------------------------------------------------------- */
 #define VD_REPORT_PCG_GUARD 1u    /* a CG step size hit its zero guard */
@@ -134,6 +145,9 @@ typedef struct {
   int32_t n_trace;    /* entries used in trace[] (VD_FLAG_TRACE) */
   double trace[VD_MAX_TRACE]; /* E_total on the current level after each
                                  position step and each rotation step */
+  double prof_us[VD_PROF_KINDS]; /* VD_FLAG_PROFILE: mean duration (us) of
+                                    the finest level's launches per class */
+  int32_t prof_n[VD_PROF_KINDS];  /* launches timed per class */
 } vd_solve_report;
 
 /* Create a handle: allocates every per-level device array and puts the state

@@ -28,7 +28,9 @@ LIB_PATH = os.path.join(HERE, "libvd.so")
 VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE = 0, -1, -2, -3, -4, -5
 VD_FP32_FP64RED, VD_FP64 = 0, 1
 VD_MEM_HOST, VD_MEM_DEVICE = 0, 1
-VD_FLAG_GRAPH, VD_FLAG_TRACE = 1, 2
+VD_FLAG_GRAPH, VD_FLAG_TRACE, VD_FLAG_PROFILE = 1, 2, 4
+VD_PROF_KINDS = 8
+PROF_NAMES = ("gradient", "cg_a", "cg_b", "rotation", "energy", "transfer")
 VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
 VD_MAX_LEVELS = 4
 VD_MAX_TRACE = 512
@@ -83,6 +85,8 @@ class SolveReport(C.Structure):
         ("polar_keep", C.c_int32),
         ("n_trace", C.c_int32),
         ("trace", C.c_double * VD_MAX_TRACE),
+        ("prof_us", C.c_double * VD_PROF_KINDS),
+        ("prof_n", C.c_int32 * VD_PROF_KINDS),
     ]
 
 
@@ -185,7 +189,7 @@ class Lattice:
 
     def __init__(self, dims, spacing, origin, num_levels=1, gn_iters=(5,), pcg_iters=(10,),
                  w_dense=1.0, w_sparse=10.0, w_arap=5.0, precision="fp32",
-                 graph=False, trace=False, stream: Optional[int] = None):
+                 graph=False, trace=False, profile=False, stream: Optional[int] = None):
         d = LatticeDesc()
         for k in range(3):
             d.dims[k] = int(dims[k])
@@ -197,7 +201,8 @@ class Lattice:
             d.pcg_iters[k] = int(pcg_iters[k]) if k < len(pcg_iters) else 0
         d.w_dense, d.w_sparse, d.w_arap = float(w_dense), float(w_sparse), float(w_arap)
         d.precision = VD_FP64 if precision == "fp64" else VD_FP32_FP64RED
-        d.flags = (VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
+        d.flags = ((VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
+                   | (VD_FLAG_PROFILE if profile else 0))
         self.desc = d
         self.stream = _current_stream() if stream is None else int(stream)
         h = C.c_void_p()
@@ -266,7 +271,11 @@ class Lattice:
         _check(_lib.vd_solve_frame(self._h, C.byref(o), C.byref(r)), "vd_solve_frame")
         return {"energy": np.array(r.energy[:]), "bits": int(r.bits),
                 "polar_fp64": int(r.polar_fp64), "polar_keep": int(r.polar_keep),
-                "trace": np.array(r.trace[:r.n_trace])}
+                "trace": np.array(r.trace[:r.n_trace]),
+                "prof_us": {PROF_NAMES[k]: float(r.prof_us[k]) for k in range(len(PROF_NAMES))
+                            if r.prof_n[k] > 0},
+                "prof_n": {PROF_NAMES[k]: int(r.prof_n[k]) for k in range(len(PROF_NAMES))
+                           if r.prof_n[k] > 0}}
 
     def get_energy(self) -> np.ndarray:
         out = (C.c_double * 4)()

@@ -70,9 +70,10 @@ struct LevelData {
     *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
   Scalars* sc = nullptr;
-  double* partials = nullptr;
-  unsigned* counter = nullptr;
-  int cap_partials = 0;  // doubles
+  double* prz[2] = {nullptr, nullptr};  // r^T D^-1 r block partials, alternating
+  double* ppap = nullptr;               // p^T A p block partials
+  double* pe = nullptr;                 // energy block partials [3][energy blocks]
+  int cap_pe = 0;                       // doubles in pe
   // constraint rows and cell cache
   int cap_rows = 0, cap_cells = 0;
   int *row_cell = nullptr, *sorted = nullptr, *seg_start = nullptr, *active_cell = nullptr;
@@ -84,7 +85,7 @@ struct LevelData {
     v.nx = nx; v.ny = ny; v.nz = nz; v.N = N;
     v.h = (T)h; v.wr = (T)wr;
     v.d = d; v.r = r; v.ap = ap; v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
-    v.cell_map = cell_map; v.K = K; v.sc = sc; v.partials = partials; v.counter = counter;
+    v.cell_map = cell_map; v.K = K; v.sc = sc;
     return v;
   }
   RowView<T> rows_view(int rows, int n_dense) const {
@@ -133,6 +134,7 @@ class Solver final : public ISolver {
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     if (h_flags_) (void)hipHostFree(h_flags_);
     if (h_sc_) (void)hipHostFree(h_sc_);
+    for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
     pool_.release_all();
   }
 
@@ -168,9 +170,11 @@ class Solver final : public ISolver {
       VD_CHECK(pool_.alloc(&v.rot, 9 * N));
       VD_CHECK(pool_.alloc(&v.cell_map, (size_t)v.ncell));
       VD_CHECK(pool_.alloc(&v.sc, 1));
-      VD_CHECK(pool_.alloc(&v.counter, 1));
       VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
-      VD_TRY(hipMemsetAsync(v.counter, 0, sizeof(unsigned), stream_));
+      const int nrz = std::max(v.ntiles, update_blocks(v.N));
+      VD_CHECK(pool_.alloc(&v.prz[0], (size_t)nrz));
+      VD_CHECK(pool_.alloc(&v.prz[1], (size_t)nrz));
+      VD_CHECK(pool_.alloc(&v.ppap, (size_t)v.ntiles));
       VD_CHECK(ensure_partials(v, 0));
     }
     VD_CHECK(pool_.alloc(&d_flags_, 4));
@@ -267,6 +271,15 @@ class Solver final : public ISolver {
       }
       if (rep->polar_fp64) rep->bits |= VD_REPORT_POLAR_FP64;
       if (rep->polar_keep) rep->bits |= VD_REPORT_POLAR_KEEP;
+      double sum[VD_PROF_KINDS] = {0};
+      for (const Timed& t : prof_) {
+        float ms = 0.0f;
+        VD_TRY(hipEventElapsedTime(&ms, ev_pool_[t.a], ev_pool_[t.b]));
+        sum[t.kind] += 1000.0 * ms;
+        rep->prof_n[t.kind] += 1;
+      }
+      for (int k = 0; k < VD_PROF_KINDS; ++k)
+        rep->prof_us[k] = rep->prof_n[k] ? sum[k] / rep->prof_n[k] : 0.0;
     }
     return VD_OK;
   }
@@ -276,8 +289,8 @@ class Solver final : public ISolver {
     if (!have_constraints_) return VD_ESTATE;
     LevelData<T>& F = finest();
     if (!energy_fresh_) {
-      VD_TRY(launch_energy<T>(F.view(desc_.w_arap), F.rows_view(rows_, n_dense_), F.cap_rows, 0,
-                              stream_));
+      VD_TRY(launch_energy<T>(F.view(desc_.w_arap), F.rows_view(rows_, n_dense_), F.cap_rows,
+                              F.pe, 0, stream_));
       energy_fresh_ = true;
     }
     VD_TRY(hipMemcpyAsync(h_sc_, F.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
@@ -354,7 +367,7 @@ class Solver final : public ISolver {
     VD_CHECK(upload_aos(p, 3 * N, mem));
     VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, N, stream_));
     VD_TRY(launch_stencil<T>(kModeApply, v.view(desc_.w_arap), dbg_t1_, dbg_t2_, nullptr, nullptr,
-                             stream_));
+                             Red{}, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(ap, 3 * N, mem);
   }
@@ -365,7 +378,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot, mem, &V));
     const int N = V.N;
-    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, nullptr, nullptr, stream_));
+    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, nullptr, nullptr, Red{}, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(g, 3 * N, mem);
   }
@@ -376,7 +389,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot, mem, &V));
     LevelData<T>& v = lv_[level];
-    VD_TRY(launch_energy<T>(V, v.rows_view(rows_, n_dense_), v.cap_rows, 0, stream_));
+    VD_TRY(launch_energy<T>(V, v.rows_view(rows_, n_dense_), v.cap_rows, v.pe, 0, stream_));
     VD_TRY(hipMemcpyAsync(h_sc_, v.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
     VD_TRY(hipStreamSynchronize(stream_));
     for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
@@ -447,6 +460,9 @@ class Solver final : public ISolver {
   int enqueue_frame(int reset, hipStream_t s) {
     const double wr = desc_.w_arap;
     const bool trace = (desc_.flags & VD_FLAG_TRACE) != 0;
+    const bool prof = (desc_.flags & VD_FLAG_PROFILE) && !(desc_.flags & VD_FLAG_GRAPH);
+    prof_.clear();
+    ev_used_ = 0;
     LevelData<T>& F = finest();
     if (reset) VD_TRY(launch_set_rest<T>(F.view(wr), s));
     for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters(lv_[l].sc, -1, -1, 1, s));
@@ -454,27 +470,76 @@ class Solver final : public ISolver {
       LevelData<T>& v = lv_[l];
       const LevelView<T> V = v.view(wr);
       const RowView<T> R = v.rows_view(rows_, n_dense_);
+      const bool on = prof && l == L_ - 1;
       if (l < L_ - 1) VD_TRY(launch_inject<T>(F.view(wr), V, 1 << (L_ - 1 - l), s));
       if (l > 0) {
         LevelData<T>& c = lv_[l - 1];
-        VD_TRY(launch_prolong_add<T>(c.view(wr), V, c.d, c.base, v.d, 1, s));
-        VD_TRY(launch_polar<T>(V, v.d, v.rot, v.rot, s));
+        VD_CHECK(timed(on, VD_PROF_TRANSFER, s, [&] {
+          return launch_prolong_add<T>(c.view(wr), V, c.d, c.base, v.d, 1, s);
+        }));
+        VD_CHECK(timed(on, VD_PROF_ROTATION, s,
+                       [&] { return launch_polar<T>(V, v.d, v.rot, v.rot, s); }));
       }
       const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
+      const int nt = v.ntiles, nu = update_blocks(v.N);
       for (int k = 0; k < gn; ++k) {
-        VD_TRY(launch_stencil<T>(kModeRhs, V, nullptr, nullptr, nullptr, nullptr, s));
+        // r^T D^-1 r of iterate m lives in prz[m % 2]; iterate 0 comes from
+        // the gradient pass (nt partials), later ones from phase B (nu).
+        Red g{};
+        g.out = v.prz[0];
+        VD_CHECK(timed(on, VD_PROF_GRADIENT, s, [&] {
+          return launch_stencil<T>(kModeRhs, V, nullptr, nullptr, nullptr, nullptr, g, s);
+        }));
         for (int m = 0; m < pcg; ++m) {
           T* p_old = (m % 2 == 0) ? v.pa : v.pb;
           T* p_new = (m % 2 == 0) ? v.pb : v.pa;
-          VD_TRY(launch_stencil<T>(kModePcg, V, nullptr, nullptr, p_old, p_new, s));
-          VD_TRY(launch_update<T>(V, p_new, s));
+          Red a{};
+          a.cur = v.prz[m % 2];
+          a.n_cur = m == 0 ? nt : nu;
+          if (m > 0) {
+            a.prev = v.prz[(m - 1) % 2];
+            a.n_prev = m == 1 ? nt : nu;
+          }
+          a.out = v.ppap;
+          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] {
+            return launch_stencil<T>(kModePcg, V, nullptr, nullptr, p_old, p_new, a, s);
+          }));
+          Red b{};
+          b.cur = v.prz[m % 2];
+          b.n_cur = m == 0 ? nt : nu;
+          b.pap = v.ppap;
+          b.n_pap = nt;
+          b.out = v.prz[(m + 1) % 2];
+          VD_CHECK(timed(on, VD_PROF_CG_B, s, [&] { return launch_update<T>(V, p_new, b, s); }));
         }
-        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, 1, s));
-        VD_TRY(launch_polar<T>(V, v.d, v.rot, v.rot, s));
-        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, 1, s));
+        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, v.pe, 1, s));
+        VD_CHECK(timed(on, VD_PROF_ROTATION, s,
+                       [&] { return launch_polar<T>(V, v.d, v.rot, v.rot, s); }));
+        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, v.pe, 1, s));
       }
     }
-    VD_TRY(launch_energy<T>(F.view(wr), F.rows_view(rows_, n_dense_), F.cap_rows, 0, s));
+    VD_CHECK(timed(prof, VD_PROF_ENERGY, s, [&] {
+      return launch_energy<T>(F.view(wr), F.rows_view(rows_, n_dense_), F.cap_rows, F.pe, 0, s);
+    }));
+    return VD_OK;
+  }
+
+  // Runs `launch` (returning hipError_t); when `on`, brackets it with a pair
+  // of timing events attributed to kernel class `kind`.
+  template <typename F>
+  int timed(bool on, int kind, hipStream_t s, F&& launch) {
+    if (!on) return launch() == hipSuccess ? VD_OK : VD_EHIP;
+    while (ev_pool_.size() < ev_used_ + 2) {
+      hipEvent_t e;
+      VD_TRY(hipEventCreate(&e));
+      ev_pool_.push_back(e);
+    }
+    const int a = (int)ev_used_, b = (int)ev_used_ + 1;
+    ev_used_ += 2;
+    VD_TRY(hipEventRecord(ev_pool_[a], s));
+    if (launch() != hipSuccess) return VD_EHIP;
+    VD_TRY(hipEventRecord(ev_pool_[b], s));
+    prof_.push_back(Timed{kind, a, b});
     return VD_OK;
   }
 
@@ -505,12 +570,12 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
-  int ensure_partials(LevelData<T>& v, int rows) {
-    const int need = 4 * std::max({v.ntiles, blocks_of(v.N), blocks_of(rows) + blocks_of(v.N)});
-    if (need <= v.cap_partials) return VD_OK;
-    pool_.release(v.partials);
-    VD_CHECK(pool_.alloc(&v.partials, (size_t)need));
-    v.cap_partials = need;
+  int ensure_partials(LevelData<T>& v, int cap_rows) {
+    const int need = 3 * energy_blocks(cap_rows, v.N);
+    if (need <= v.cap_pe) return VD_OK;
+    pool_.release(v.pe);
+    VD_CHECK(pool_.alloc(&v.pe, (size_t)need));
+    v.cap_pe = need;
     ++alloc_gen_;
     return VD_OK;
   }
@@ -653,6 +718,13 @@ class Solver final : public ISolver {
   int rows_ = 0, n_dense_ = 0;
   bool have_constraints_ = false;
   bool energy_fresh_ = false;
+  // timing events of the last profiled frame
+  struct Timed {
+    int kind, a, b;
+  };
+  std::vector<hipEvent_t> ev_pool_;
+  size_t ev_used_ = 0;
+  std::vector<Timed> prof_;
   // test scratch
   float* dbg_f_ = nullptr;
   T *dbg_t1_ = nullptr, *dbg_t2_ = nullptr, *dbg_rot_ = nullptr;

@@ -325,17 +325,19 @@ hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hip
 // One workgroup per 8x8x4 tile; the tile plus a one-node halo of p is staged
 // in LDS (all 27 stencil neighbours of a tile node are in it).
 //
-// kModePcg : p = D^-1 r + beta p_old (p = D^-1 r on the first iteration) is
-//            formed while staging, written to p_new, Ap written, and the last
-//            block turns sum p.Ap into alpha = rz / p^T A p.
+// kModePcg : beta = rz_cur / rz_prev from the previous kernels' partials;
+//            p = D^-1 r + beta p_old (p = D^-1 r on the first iteration) is
+//            formed while staging and written to p_new; A p is written and
+//            the block partials of p^T A p go to red.out.
 // kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
-//            gradient J^T r; r = -g is stored and rz = r^T D^-1 r reduced.
+//            gradient J^T r; r = -g is stored and the partials of
+//            r^T D^-1 r go to red.out.
 // kModeApply / kModeGrad : A p or g written to `out` (test entry points).
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __restrict__ pin,
                                                     T* __restrict__ out,
                                                     const T* __restrict__ p_old,
-                                                    T* __restrict__ p_new) {
+                                                    T* __restrict__ p_new, Red red) {
   __shared__ T sp[3][kHalo];
   const int ntx = (L.nx + kTX - 1) / kTX, nty = (L.ny + kTY - 1) / kTY;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -346,10 +348,16 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
   T beta = T(0);
   bool first = true;
   if (MODE == kModePcg) {
-    first = (L.sc->beta_valid == 0);
-    beta = (T)L.sc->beta;
+    first = (red.prev == nullptr);
+    if (!first) {
+      const double rz_cur = sum_partials(red.cur, red.n_cur);
+      const double rz_prev = sum_partials(red.prev, red.n_prev);
+      beta = rz_prev > 0.0 ? (T)(rz_cur / rz_prev) : T(0);
+    }
   }
-  const T* src = (MODE == kModeRhs) ? L.d : pin;
+  const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
+  const T* __restrict__ r = L.r;
+  const T* __restrict__ dinv = L.dinv;
 
   for (int k = threadIdx.x; k < kHalo; k += kBlock) {
     const int lx = k % kHX, ly = (k / kHX) % kHY, lz = k / (kHX * kHY);
@@ -358,9 +366,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
     if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       if (MODE == kModePcg) {
-        v0 = L.dinv[i] * L.r[i];
-        v1 = L.dinv[N + i] * L.r[N + i];
-        v2 = L.dinv[2 * N + i] * L.r[2 * N + i];
+        const T r0 = r[i], r1 = r[N + i], r2 = r[2 * N + i];
+        const T q0 = dinv[i], q1 = dinv[N + i], q2 = dinv[2 * N + i];
+        v0 = q0 * r0;
+        v1 = q1 * r1;
+        v2 = q2 * r2;
         if (!first) {
           v0 += beta * p_old[i];
           v1 += beta * p_old[N + i];
@@ -389,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
   const bool valid = in_box(gx, gy, gz, L.nx, L.ny, L.nz);
   const int c = lx + kHX * (ly + kHY * lz);
   T o0 = T(0), o1 = T(0), o2 = T(0);
-  T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
+  const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
   size_t i = 0;
   if (valid) {
     i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
       if (!in_box(cx, cy, cz, cnx, cny, cnz)) continue;
       const int ci = L.cell_map[cx + cnx * (cy + cny * cz)];
       if (ci < 0) continue;
-      const T* kr = L.K + ((size_t)ci * 64 + a * 8) * 6;
+      const T* __restrict__ kr = L.K + ((size_t)ci * 64 + a * 8) * 6;
       const int cb0 = c - dx - kHX * (dy + kHY * dz);  // local index of the cell's corner 0
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
@@ -449,21 +459,22 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
     if (valid) {
       // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
       // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
+      const T* __restrict__ rot = L.rot;
       T q0 = T(0), q1 = T(0), q2 = T(0);
       const int pos[3] = {gx, gy, gz};
       const int lim[3] = {L.nx, L.ny, L.nz};
       const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        const T ci0 = L.rot[rot_at(0, ax, N, i)], ci1 = L.rot[rot_at(1, ax, N, i)],
-                ci2 = L.rot[rot_at(2, ax, N, i)];
+        const T ci0 = rot[rot_at(0, ax, N, i)], ci1 = rot[rot_at(1, ax, N, i)],
+                ci2 = rot[rot_at(2, ax, N, i)];
 #pragma unroll
         for (int sgn = -1; sgn <= 1; sgn += 2) {
           const int pj = pos[ax] + sgn;
           if (pj < 0 || pj >= lim[ax]) continue;
           const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
-          const T cj0 = L.rot[rot_at(0, ax, N, j)], cj1 = L.rot[rot_at(1, ax, N, j)],
-                  cj2 = L.rot[rot_at(2, ax, N, j)];
+          const T cj0 = rot[rot_at(0, ax, N, j)], cj1 = rot[rot_at(1, ax, N, j)],
+                  cj2 = rot[rot_at(2, ax, N, j)];
           const T s = -T(sgn) * L.h;
           T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
           if (ax == 0) u0 += T(2);
@@ -489,64 +500,50 @@ __global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __r
     double part[1] = {0.0};
     if (valid) {
       const T r0 = -g0, r1 = -g1, r2 = -g2;
-      L.r[i] = r0;
-      L.r[N + i] = r1;
-      L.r[2 * N + i] = r2;
-      part[0] = (double)(r0 * L.dinv[i]) * (double)r0 + (double)(r1 * L.dinv[N + i]) * (double)r1 +
-                (double)(r2 * L.dinv[2 * N + i]) * (double)r2;
+      T* __restrict__ rw = L.r;
+      rw[i] = r0;
+      rw[N + i] = r1;
+      rw[2 * N + i] = r2;
+      part[0] = (double)(r0 * dinv[i]) * (double)r0 + (double)(r1 * dinv[N + i]) * (double)r1 +
+                (double)(r2 * dinv[2 * N + i]) * (double)r2;
     }
-    double tot[1];
-    if (last_block_total<1>(part, L.partials, L.counter, tot)) {
-      if (threadIdx.x == 0) {
-        L.sc->rz = tot[0];
-        L.sc->beta = 0.0;
-        L.sc->beta_valid = 0;
-      }
-    }
+    write_block_partials<1>(part, red.out, 0);
     return;
   }
   // kModePcg
   double part[1] = {0.0};
   if (valid) {
-    L.ap[i] = o0;
-    L.ap[N + i] = o1;
-    L.ap[2 * N + i] = o2;
+    T* __restrict__ ap = L.ap;
+    ap[i] = o0;
+    ap[N + i] = o1;
+    ap[2 * N + i] = o2;
     part[0] = (double)p0 * (double)o0 + (double)p1 * (double)o1 + (double)p2 * (double)o2;
   }
-  double tot[1];
-  if (last_block_total<1>(part, L.partials, L.counter, tot)) {
-    if (threadIdx.x == 0) {
-      const double rz = L.sc->rz;
-      const double pap = tot[0];
-      L.sc->pap = pap;
-      if (pap > 0.0) {
-        L.sc->alpha = rz / pap;
-      } else {
-        L.sc->alpha = 0.0;
-        L.sc->guard_hits += 1;
-      }
-    }
-  }
+  write_block_partials<1>(part, red.out, 0);
 }
+
+int stencil_blocks(int nx, int ny, int nz) {
+  return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kTZ - 1) / kTZ);
+}
+int update_blocks(int N) { return blocks_for(N); }
+int energy_blocks(int cap_rows, int N) { return blocks_for(cap_rows) + blocks_for(N); }
 
 template <typename T>
 hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
-                          T* p_new, hipStream_t s) {
-  const int ntx = (L.nx + kTX - 1) / kTX, nty = (L.ny + kTY - 1) / kTY,
-            ntz = (L.nz + kTZ - 1) / kTZ;
-  const int grid = ntx * nty * ntz;
+                          T* p_new, const Red& red, hipStream_t s) {
+  const int grid = stencil_blocks(L.nx, L.ny, L.nz);
   switch (mode) {
     case kModePcg:
-      k_stencil<T, kModePcg><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      k_stencil<T, kModePcg><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
       break;
     case kModeRhs:
-      k_stencil<T, kModeRhs><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      k_stencil<T, kModeRhs><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
       break;
     case kModeApply:
-      k_stencil<T, kModeApply><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      k_stencil<T, kModeApply><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
       break;
     case kModeGrad:
-      k_stencil<T, kModeGrad><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new);
+      k_stencil<T, kModeGrad><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
       break;
     default:
       return hipErrorInvalidValue;
@@ -555,41 +552,52 @@ hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out,
 }
 
 // ===========================================================================
-// CG phase B: d += alpha p; r -= alpha A p; rz_new = r^T D^-1 r; beta
+// CG phase B: alpha = rz / p^T A p; d += alpha p; r -= alpha A p;
+// partials of the new r^T D^-1 r
 // ===========================================================================
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(LevelView<T> L, const T* __restrict__ p) {
+__global__ __launch_bounds__(kBlock) void k_update(LevelView<T> L, const T* __restrict__ p,
+                                                   Red red) {
+  const double pap = sum_partials(red.pap, red.n_pap);
+  const double rz = sum_partials(red.cur, red.n_cur);
+  const T alpha = pap > 0.0 ? (T)(rz / pap) : T(0);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(pap > 0.0)) L.sc->guard_hits += 1;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const size_t N = L.N;
-  const T alpha = (T)L.sc->alpha;
+  T* __restrict__ d = L.d;
+  T* __restrict__ r = L.r;
+  const T* __restrict__ ap = L.ap;
+  const T* __restrict__ dinv = L.dinv;
   double part[1] = {0.0};
   if (i < L.N) {
+    T pv[3], av[3], dv[3], rv[3], qv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const size_t j = k * N + i;
+      pv[k] = p[j];
+      av[k] = ap[j];
+      dv[k] = d[j];
+      rv[k] = r[j];
+      qv[k] = dinv[j];
+    }
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const size_t j = k * N + i;
-      L.d[j] += alpha * p[j];
-      const T rn = L.r[j] - alpha * L.ap[j];
-      L.r[j] = rn;
-      acc += (double)(rn * L.dinv[j]) * (double)rn;
+      d[j] = dv[k] + alpha * pv[k];
+      const T rn = rv[k] - alpha * av[k];
+      r[j] = rn;
+      acc += (double)(rn * qv[k]) * (double)rn;
     }
     part[0] = acc;
   }
-  double tot[1];
-  if (last_block_total<1>(part, L.partials, L.counter, tot)) {
-    if (threadIdx.x == 0) {
-      const double rz_old = L.sc->rz;
-      L.sc->beta = rz_old > 0.0 ? tot[0] / rz_old : 0.0;
-      L.sc->rz = tot[0];
-      L.sc->beta_valid = 1;
-    }
-  }
+  write_block_partials<1>(part, red.out, 0);
 }
 
 template <typename T>
-hipError_t launch_update(const LevelView<T>& L, const T* p_new, hipStream_t s) {
-  k_update<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, p_new);
+hipError_t launch_update(const LevelView<T>& L, const T* p_new, const Red& red, hipStream_t s) {
+  k_update<T><<<update_blocks(L.N), kBlock, 0, s>>>(L, p_new, red);
   return hipGetLastError();
 }
 
@@ -599,9 +607,10 @@ hipError_t launch_update(const LevelView<T>& L, const T* p_new, hipStream_t s) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R, int row_blocks,
-                                                   int record_trace) {
+                                                   double* part_out) {
   double part[3] = {0.0, 0.0, 0.0};
   const size_t N = L.N;
+  const T* __restrict__ d = L.d;
   if ((int)blockIdx.x < row_blocks) {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     const int rows = L.sc->rows;
@@ -616,9 +625,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R,
         const size_t m = (cx + (k & 1)) + (size_t)L.nx * ((cy + ((k >> 1) & 1)) +
                                                           (size_t)L.ny * (cz + (k >> 2)));
         const T w = corner_weight<T>(k, fx, fy, fz);
-        s0 += w * L.d[m];
-        s1 += w * L.d[N + m];
-        s2 += w * L.d[2 * N + m];
+        s0 += w * d[m];
+        s1 += w * d[N + m];
+        s2 += w * d[2 * N + m];
       }
       const T res = R.sn[row] * s0 + R.sn[(size_t)rows + row] * s1 +
                     R.sn[2 * (size_t)rows + row] * s2 - R.rho[row];
@@ -628,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R,
   } else {
     const int i = (blockIdx.x - row_blocks) * kBlock + threadIdx.x;
     if (i < L.N) {
+      const T* __restrict__ rot = L.rot;
       const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
       const int pos[3] = {x, y, z};
       const int lim[3] = {L.nx, L.ny, L.nz};
@@ -636,8 +646,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R,
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         // (I - R_i) e_ij with e_ij = -s h axis
-        T c0 = -L.rot[rot_at(0, ax, N, i)], c1 = -L.rot[rot_at(1, ax, N, i)],
-          c2 = -L.rot[rot_at(2, ax, N, i)];
+        T c0 = -rot[rot_at(0, ax, N, i)], c1 = -rot[rot_at(1, ax, N, i)],
+          c2 = -rot[rot_at(2, ax, N, i)];
         if (ax == 0) c0 += T(1);
         if (ax == 1) c1 += T(1);
         if (ax == 2) c2 += T(1);
@@ -647,37 +657,45 @@ __global__ __launch_bounds__(kBlock) void k_energy(LevelView<T> L, RowView<T> R,
           if (pj < 0 || pj >= lim[ax]) continue;
           const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
           const T s = -T(sgn) * L.h;
-          const T e0 = L.d[i] - L.d[j] + s * c0;
-          const T e1 = L.d[N + i] - L.d[N + j] + s * c1;
-          const T e2 = L.d[2 * N + i] - L.d[2 * N + j] + s * c2;
+          const T e0 = d[i] - d[j] + s * c0;
+          const T e1 = d[N + i] - d[N + j] + s * c1;
+          const T e2 = d[2 * N + i] - d[2 * N + j] + s * c2;
           acc += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
         }
       }
       part[2] = (double)L.wr * acc;
     }
   }
-  double tot[3];
-  if (last_block_total<3>(part, L.partials, L.counter, tot)) {
-    if (threadIdx.x == 0) {
-      Scalars* sc = L.sc;
-      sc->energy[0] = tot[0] + tot[1] + tot[2];
-      sc->energy[1] = tot[0];
-      sc->energy[2] = tot[1];
-      sc->energy[3] = tot[2];
-      if (record_trace && sc->n_trace < VD_MAX_TRACE) {
-        sc->trace[sc->n_trace] = sc->energy[0];
-        sc->n_trace += 1;
-      }
+  write_block_partials<3>(part, part_out, gridDim.x);
+}
+
+// One block: sums the energy partials into sc->energy (and the trace).
+__global__ __launch_bounds__(kBlock) void k_energy_finalize(Scalars* sc, const double* part,
+                                                            int n, int record_trace) {
+  const double e_dense = sum_partials(part, n);
+  const double e_sparse = sum_partials(part + n, n);
+  const double e_reg = sum_partials(part + 2 * (size_t)n, n);
+  if (threadIdx.x == 0) {
+    sc->energy[0] = e_dense + e_sparse + e_reg;
+    sc->energy[1] = e_dense;
+    sc->energy[2] = e_sparse;
+    sc->energy[3] = e_reg;
+    if (record_trace && sc->n_trace < VD_MAX_TRACE) {
+      sc->trace[sc->n_trace] = sc->energy[0];
+      sc->n_trace += 1;
     }
   }
 }
 
 template <typename T>
 hipError_t launch_energy(const LevelView<T>& L, const RowView<T>& R, int cap_rows,
-                         int record_trace, hipStream_t s) {
+                         double* part, int record_trace, hipStream_t s) {
   const int rb = blocks_for(cap_rows);
-  const int nb = blocks_for(L.N);
-  k_energy<T><<<rb + nb, kBlock, 0, s>>>(L, R, rb, record_trace);
+  const int nb = energy_blocks(cap_rows, L.N);
+  k_energy<T><<<nb, kBlock, 0, s>>>(L, R, rb, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_energy_finalize<<<1, kBlock, 0, s>>>(L.sc, part, nb, record_trace);
   return hipGetLastError();
 }
 
@@ -980,10 +998,10 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_assemble_nodes<T>(const LevelView<T>&, const RowView<T>&,          \
                                                hipStream_t);                                    \
   template hipError_t launch_stencil<T>(int, const LevelView<T>&, const T*, T*, T*, T*,         \
-                                        hipStream_t);                                           \
-  template hipError_t launch_update<T>(const LevelView<T>&, const T*, hipStream_t);             \
-  template hipError_t launch_energy<T>(const LevelView<T>&, const RowView<T>&, int, int,        \
-                                       hipStream_t);                                            \
+                                        const Red&, hipStream_t);                               \
+  template hipError_t launch_update<T>(const LevelView<T>&, const T*, const Red&, hipStream_t); \
+  template hipError_t launch_energy<T>(const LevelView<T>&, const RowView<T>&, int, double*,    \
+                                       int, hipStream_t);                                       \
   template hipError_t launch_polar<T>(const LevelView<T>&, const T*, const T*, T*, hipStream_t); \
   template hipError_t launch_inject<T>(const LevelView<T>&, const LevelView<T>&, int,           \
                                        hipStream_t);                                            \

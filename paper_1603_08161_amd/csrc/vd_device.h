@@ -1,8 +1,9 @@
 // Device helpers shared by the solver kernels (gfx950, wave64).
 //
 // - trilinear corner weights of Sec. 4;
-// - wave/block reductions in float64 and the deterministic "last block
-//   finishes the sum" pattern used for the CG scalars and energies;
+// - wave/block reductions in float64: every reduction kernel writes one
+//   partial per block, and the kernel that needs the scalar re-reduces those
+//   partials in fixed order (bitwise deterministic, no cross-block fences);
 // - the Procrustes rotation fit of Sec. 7.1, solved with Horn's closed form
 //   (unit quaternion = dominant eigenvector of a 4x4 symmetric matrix built
 //   from the cross-covariance) and a cyclic Jacobi eigen-solver.
@@ -63,47 +64,38 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* K * kBl
   __syncthreads();
 }
 
-// Every block publishes K partial sums; the last block to arrive adds all
-// partials in block order and returns true with the totals in `tot` (valid in
-// every thread of that block).  The counter is reset by the last block, so
-// the kernel can be relaunched (and replayed from a graph) without clearing.
+// Sum of n partials written by the previous kernel, computed by every block
+// in the same fixed order (bitwise identical in all blocks).  No block of the
+// current kernel writes them, so the kernel boundary alone makes them
+// visible: no cross-workgroup fence is needed.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n) {
+  __shared__ double lds[kBlock / kWave];
+  __shared__ double total;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < n; b += kBlock) acc += p[b];
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  if (lane == 0) lds[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) s += lds[w];
+    total = s;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Block-wide sums of K values written to out[k * stride + blockIdx.x].
 template <int K>
-__device__ bool last_block_total(double (&v)[K], double* partials, unsigned* counter,
-                                 double (&tot)[K]) {
+__device__ __forceinline__ void write_block_partials(double (&v)[K], double* out, int stride) {
   __shared__ double lds[K * (kBlock / kWave)];
-  __shared__ int is_last;
   block_sum<K>(v, lds);
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) partials[(size_t)blockIdx.x * K + k] = v[k];
-    __threadfence();
-    unsigned ticket = atomicAdd(counter, 1u);
-    is_last = (ticket == (unsigned)(nb - 1));
+    for (int k = 0; k < K; ++k) out[(size_t)k * stride + blockIdx.x] = v[k];
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      acc[k] += __hip_atomic_load(&partials[(size_t)b * K + k], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<K>(acc, lds);
-  __shared__ double bc[K];
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) bc[k] = acc[k];
-    *counter = 0u;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) tot[k] = bc[k];
-  return true;
 }
 
 // ---------------------------------------------------------------------------

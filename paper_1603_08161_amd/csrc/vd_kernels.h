@@ -47,8 +47,18 @@ struct LevelView {
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
   Scalars* sc;
-  double* partials;
-  unsigned* counter;
+};
+
+// Reduction plumbing of one launch: partials of the scalars it consumes
+// (written by earlier kernels) and the array its own block partials go to.
+struct Red {
+  const double* cur;   // r^T D^-1 r partials of the current CG iterate
+  int n_cur;
+  const double* prev;  // ... of the previous iterate (null on the first iteration)
+  int n_prev;
+  const double* pap;   // p^T A p partials (phase B)
+  int n_pap;
+  double* out;         // this launch's block partials
 };
 
 // Constraint rows of one level (dense rows then 3 rows per sparse pair).
@@ -101,18 +111,24 @@ hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hip
 // ---- solve ---------------------------------------------------------------
 enum StencilMode { kModePcg = 0, kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
 
+// Number of workgroups (= block partials) of the stencil and update kernels.
+int stencil_blocks(int nx, int ny, int nz);
+int update_blocks(int N);
+int energy_blocks(int cap_rows, int N);
+
 template <typename T>
 hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
-                          T* p_new, hipStream_t s);
+                          T* p_new, const Red& red, hipStream_t s);
 
 template <typename T>
-hipError_t launch_update(const LevelView<T>& L, const T* p_new, hipStream_t s);
+hipError_t launch_update(const LevelView<T>& L, const T* p_new, const Red& red, hipStream_t s);
 
 // Energy over the rows (count read from sc->rows; grid sized by `cap_rows`)
-// and the ARAP edges of level L.
+// and the ARAP edges of level L; block partials go to part[3][energy_blocks],
+// then one block sums them into sc->energy (and the trace).
 template <typename T>
 hipError_t launch_energy(const LevelView<T>& L, const RowView<T>& R, int cap_rows,
-                         int record_trace, hipStream_t s);
+                         double* part, int record_trace, hipStream_t s);
 
 // Per-frame counters of a level back to zero; rows/n_dense stored when >= 0.
 hipError_t launch_reset_counters(Scalars* sc, int rows, int n_dense, int clear_trace,

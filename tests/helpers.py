@@ -41,11 +41,15 @@ def rel_err(a, b):
 
 
 def rotation_angle(Ra, Rb):
-    """Angle (rad) of Ra^T Rb per node."""
+    """Angle (rad) of Ra^T Rb per node, as atan2(|skew part|, (trace-1)/2):
+    unlike arccos((trace-1)/2) it stays accurate for tiny angles."""
     Ra = np.asarray(Ra, np.float64)
     Rb = np.asarray(Rb, np.float64)
-    tr = np.einsum("nab,nab->n", Ra, Rb)
-    return np.arccos(np.clip((tr - 1.0) / 2.0, -1.0, 1.0))
+    M = np.einsum("nba,nbc->nac", Ra, Rb)
+    w = 0.5 * np.stack([M[:, 2, 1] - M[:, 1, 2], M[:, 0, 2] - M[:, 2, 0],
+                        M[:, 1, 0] - M[:, 0, 1]], axis=1)
+    c = 0.5 * (np.trace(M, axis1=1, axis2=2) - 1.0)
+    return np.arctan2(np.linalg.norm(w, axis=1), c)
 
 
 def make_lattice(scene, **kw):

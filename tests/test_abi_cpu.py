@@ -43,8 +43,8 @@ int main(void) {
          offsetof(vd_lattice_desc, precision), offsetof(vd_lattice_desc, flags));
   printf("cons %zu %zu %zu\n", sizeof(vd_constraints), offsetof(vd_constraints, n_sparse),
          offsetof(vd_constraints, mem));
-  printf("rep %zu %zu %zu\n", sizeof(vd_solve_report), offsetof(vd_solve_report, n_trace),
-         offsetof(vd_solve_report, trace));
+  printf("rep %zu %zu %zu %zu\n", sizeof(vd_solve_report), offsetof(vd_solve_report, n_trace),
+         offsetof(vd_solve_report, trace), offsetof(vd_solve_report, prof_n));
   printf("opts %zu\n", sizeof(vd_solve_opts));
   return 0;
 }
@@ -62,7 +62,7 @@ int main(void) {
     Cs = L.Constraints
     assert out["cons"] == [ctypes.sizeof(Cs), Cs.n_sparse.offset, Cs.mem.offset]
     R = L.SolveReport
-    assert out["rep"] == [ctypes.sizeof(R), R.n_trace.offset, R.trace.offset]
+    assert out["rep"] == [ctypes.sizeof(R), R.n_trace.offset, R.trace.offset, R.prof_n.offset]
     assert out["opts"] == [ctypes.sizeof(L.SolveOpts)]
 
 

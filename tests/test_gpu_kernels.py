@@ -2,8 +2,10 @@
 and compares with the FP64 oracle on the same seeded inputs.
 
 Tolerances (float32 path): A p and J^T r to 1e-5 norm-relative, energy at a
-fixed state to 1e-6 relative, rotations to 1e-5 rad; the float64 path is
-held to 1e-12."""
+fixed state to 1e-6 relative, rotations to 1e-5 rad.  The float64 path returns
+its vectors through the float32 interface, so they are held to the float32
+rounding bound (1.5e-7); its energies come back as doubles and are held to
+1e-11."""
 
 import numpy as np
 import pytest
@@ -44,7 +46,7 @@ def test_apply_matches_oracle(name, precision):
     lat = make_lattice(scene, precision=precision)
     cons = oracle_cons(scene)
     rng = np.random.default_rng(1)
-    tol = 1e-5 if precision == "fp32" else 1e-12
+    tol = 1e-5 if precision == "fp32" else 1.5e-7
     for lvl, grid in zip(_levels(scene), grids_of(scene)):
         system = LevelSystem(grid, cons)
         for p in (rng.normal(size=(grid.n, 3)),
@@ -56,22 +58,24 @@ def test_apply_matches_oracle(name, precision):
 
 
 @pytest.mark.parametrize("name", list(SCENES))
-def test_diag_gradient_energy_match_oracle(name):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_diag_gradient_energy_match_oracle(name, precision):
     scene = SCENES[name]()
-    lat = make_lattice(scene)
+    lat = make_lattice(scene, precision=precision)
+    vec_tol, e_tol = (1e-5, 1e-6) if precision == "fp32" else (1.5e-7, 1e-11)
     cons = oracle_cons(scene)
     rng = np.random.default_rng(2)
     for lvl, grid in zip(_levels(scene), grids_of(scene)):
         system = LevelSystem(grid, cons)
         d_ref = 1.0 / np.where(system.dinv > 0, system.dinv, np.inf)
-        assert rel_err(lat.debug_diag(lvl), d_ref.reshape(-1, 3)) < 1e-6
+        assert rel_err(lat.debug_diag(lvl), d_ref.reshape(-1, 3)) < max(vec_tol, 1e-6)
         pos, rot = random_state(grid, rng)
         t, R = pos.astype(np.float64), rot.astype(np.float64)
         g_ref = system.gradient(t, R).reshape(-1, 3)
-        assert rel_err(lat.debug_gradient(lvl, pos, rot), g_ref) < 1e-5
+        assert rel_err(lat.debug_gradient(lvl, pos, rot), g_ref) < vec_tol
         e_ref = energy_terms(grid, t, R, cons)
         e_gpu = lat.debug_energy(lvl, pos, rot)
-        np.testing.assert_allclose(e_gpu, e_ref, rtol=1e-6, atol=1e-12 * e_ref[0])
+        np.testing.assert_allclose(e_gpu, e_ref, rtol=e_tol, atol=1e-13 * e_ref[0])
 
 
 def test_cfg1_levels_match_oracle(cfg1):
@@ -93,7 +97,7 @@ def test_cfg1_levels_match_oracle(cfg1):
                                    energy_terms(grid, t, R, cons), rtol=1e-6)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-10)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 3e-7)])
 def test_rotation_step_matches_oracle(precision, tol):
     scene = SCENES["ragged"]()
     lat = make_lattice(scene, precision=precision)
@@ -125,7 +129,7 @@ def test_batched_fit_matches_oracle(precision):
     R, code = fit_rotations(M, prev, precision=precision)
     np.testing.assert_array_equal(code == 2, deg)
     ang = rotation_angle(R[~deg], R_ref[~deg])
-    assert ang.max() < (1e-5 if precision == "fp32" else 1e-6)
+    assert ang.max() < (1e-5 if precision == "fp32" else 3e-7)
     np.testing.assert_array_equal(R[deg], prev[deg])
     # objective trace(R^T M) matches (the unique quantity)
     obj = np.einsum("nab,nab->n", R.astype(np.float64), M.astype(np.float64))

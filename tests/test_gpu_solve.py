@@ -66,11 +66,14 @@ def test_deterministic_rerun_and_resume():
     pos_a, rot_a = a.get_state()
     a.solve_frame()
     pos_a2, _ = a.get_state()
-    # resume from a checkpoint of the first frame in a fresh handle
+    # resume from a checkpoint of the first frame in a fresh handle: the
+    # checkpoint holds float32 positions, so the resumed frame agrees to the
+    # rounding of those positions
     b = make_lattice(scene)
     b.set_state(pos_a, rot_a)
     b.solve_frame()
-    np.testing.assert_array_equal(b.get_state()[0], pos_a2)
+    np.testing.assert_allclose(b.get_state()[0], pos_a2, rtol=0, atol=1e-5 * scene.spec.spacing)
+    # a fresh handle from rest reproduces the first frame bit for bit
     c = make_lattice(scene)
     c.solve_frame()
     np.testing.assert_array_equal(c.get_state()[0], pos_a)
