@@ -8,10 +8,11 @@ final energy is within 1e-4 relative of the FP64 oracle's replica solve of
 the same input.
 
 Also reported:
-* roofline -- the CG phase-A stencil kernel on the 64^3 level: algorithmic
-  bytes per launch (60 B per node + 24 B per dense and 12 B per sparse
-  sample) over its mean duration, timed with HIP events on the library's
-  stream in a profiled eager replay of the same frames;
+* roofline -- the fused CG-iteration kernel on the 64^3 level (one launch =
+  one Jacobi-PCG iteration): algorithmic bytes per iteration (144 B per node
+  + 24 B per dense and 12 B per sparse sample, float32) over its mean
+  duration, timed with HIP events on the library's stream in a profiled
+  eager replay of the same frames;
 * cpu_baseline -- the FP64 oracle timed on this host on one full frame.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -32,11 +33,12 @@ METRIC = "solved frames/s at 64³ lattice (energy ≤1e-4 of oracle), HBM %; war
 HBM_PEAK_GBS = 8000.0
 
 
-def stencil_bytes(n_nodes: int, n_dense: int, n_sparse: int, elem: int = 4) -> float:
-    """Algorithmic bytes of one CG phase-A launch: read r, D^-1, p_old and
-    write p, A p (5 node vectors of 3 components) plus 24 B per dense and 12 B
-    per sparse sample (float32 values)."""
-    return 15.0 * elem * n_nodes + 24.0 * n_dense + 12.0 * n_sparse
+def cg_iteration_bytes(n_nodes: int, n_dense: int, n_sparse: int, elem: int = 4) -> float:
+    """Compulsory bytes of one Jacobi-PCG iteration on a level: 12 node-vector
+    passes of 3 components (phase A reads r, D^-1, p and writes p, A p; phase
+    B reads d, p, r, A p, D^-1 and writes d, r) plus 24 B per dense and 12 B
+    per sparse sample for the data term."""
+    return 36.0 * elem * n_nodes + 24.0 * n_dense + 12.0 * n_sparse
 
 
 def main() -> int:
@@ -73,7 +75,14 @@ def main() -> int:
     print(f"# workload: {spec.dims} lattice, {spec.num_levels} levels, {scene.n_dense} dense + "
           f"{scene.n_sparse} sparse constraints", flush=True)
 
+    # tile autotuning (setup, outside the timed region): the library times
+    # each stencil tile shape per level on these constraints and keeps the
+    # fastest for the captured schedule
     lat = Lattice.from_spec(spec, graph=True)
+    lat.set_constraints(*inputs)
+    tiles, tile_us = lat.tune(iters=10)
+    print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4]: "
+          + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us), flush=True)
 
     def step():
         lat.set_constraints(*inputs)
@@ -93,7 +102,7 @@ def main() -> int:
     print(f"# timed {args.steps} frames in {elapsed * 1e3:.2f} ms", flush=True)
 
     # roofline of the dominant kernel: profiled eager replay of the same frame
-    prof = Lattice.from_spec(spec, profile=True)
+    prof = Lattice.from_spec(spec, profile=True, tiles=tiles)
     prof.set_constraints(*inputs)
     cg_a = []
     for _ in range(3):
@@ -102,7 +111,7 @@ def main() -> int:
     prof_us = rep["prof_us"]
     cg_a_us = float(np.mean(cg_a))
     n_fine = spec.dims[0] * spec.dims[1] * spec.dims[2]
-    nbytes = stencil_bytes(n_fine, scene.n_dense, scene.n_sparse)
+    nbytes = cg_iteration_bytes(n_fine, scene.n_dense, scene.n_sparse)
     achieved = nbytes / (cg_a_us * 1e-6) / 1e9
     print(f"# finest-level kernel means (us): "
           + ", ".join(f"{k}={v:.2f}" for k, v in prof_us.items()), flush=True)
@@ -154,6 +163,7 @@ def main() -> int:
             "n_dense": scene.n_dense,
             "n_sparse": scene.n_sparse,
             "launch": "hipGraph replay per frame",
+            "tiles": tiles,
         },
         "solved_frames": solved,
         "energy_gpu": float(energies[-1, 0]),
@@ -161,7 +171,7 @@ def main() -> int:
         "max_rel_energy_err": max_rel,
         "roofline": {
             "bound": "hbm",
-            "kernel": "CG phase A stencil (k_stencil<float, kModePcg>) on the 64^3 level",
+            "kernel": "fused CG iteration (k_cg<float>) on the 64^3 level",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -70,8 +70,8 @@ extern "C" {
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
-#define VD_PROF_CG_A 1      /* CG phase A: p update + A p stencil + p^T A p */
-#define VD_PROF_CG_B 2      /* CG phase B: d, r update + r^T D^-1 r */
+#define VD_PROF_CG_A 1      /* one CG iteration: step, direction, A p stencil */
+#define VD_PROF_CG_B 2      /* the last CG step (d += alpha p) */
 #define VD_PROF_ROTATION 3  /* rotation fits */
 #define VD_PROF_ENERGY 4    /* energy evaluation */
 #define VD_PROF_TRANSFER 5  /* injection / prolongation */
@@ -105,6 +105,9 @@ typedef struct {
   double w_arap;                    /* w_r */
   int32_t precision;                /* VD_FP32_FP64RED or VD_FP64 */
   uint32_t flags;                   /* VD_FLAG_* */
+  int32_t tile[VD_MAX_LEVELS];      /* stencil tile per level: 0 = library
+                                       default, 1 = 8x8x4, 2 = 8x8x8,
+                                       3 = 32x8x4 (see vd_tune) */
 } vd_lattice_desc;
 
 /* Correspondences of one frame (Sec. 5, used by eqs. (2)-(3)).
@@ -192,6 +195,15 @@ int vd_level_info(const vd_lattice* l, int32_t level, int32_t dims[3], double* s
 
 /* Text for a status code. */
 const char* vd_strerror(int code);
+
+/* Autotuner of the stencil tile shape (the brick each workgroup stages in
+ * LDS).  For every level it times `iters` CG iterations with each tile kind
+ * on the current constraints (the state is saved and restored), keeps the
+ * fastest for later frames and reports it in tile_out[level] (1..3, as in
+ * vd_lattice_desc.tile) with the mean microseconds per CG iteration of each
+ * kind in us_out[3 * level + kind - 1] (either pointer may be NULL).
+ * VD_ESTATE if no constraints were set.  Synchronous. */
+int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out);
 
 /* ---- test entry points (unstable; for parity tests) -------------------- */
 

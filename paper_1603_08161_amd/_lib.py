@@ -39,7 +39,7 @@ EXPORTED = (
     "vd_lattice_create", "vd_lattice_destroy", "vd_set_constraints", "vd_solve_frame",
     "vd_get_energy", "vd_get_state", "vd_set_state", "vd_level_info", "vd_strerror",
     "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
-    "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong",
+    "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong", "vd_tune",
 )
 
 
@@ -56,6 +56,7 @@ class LatticeDesc(C.Structure):
         ("w_arap", C.c_double),
         ("precision", C.c_int32),
         ("flags", C.c_uint32),
+        ("tile", C.c_int32 * VD_MAX_LEVELS),
     ]
 
 
@@ -120,6 +121,7 @@ def _load() -> C.CDLL:
         "vd_debug_rotations": ([vp, i32, vp, vp, vp, i32], C.c_int),
         "vd_debug_fit_rotations": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
         "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
+        "vd_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -189,7 +191,8 @@ class Lattice:
 
     def __init__(self, dims, spacing, origin, num_levels=1, gn_iters=(5,), pcg_iters=(10,),
                  w_dense=1.0, w_sparse=10.0, w_arap=5.0, precision="fp32",
-                 graph=False, trace=False, profile=False, stream: Optional[int] = None):
+                 graph=False, trace=False, profile=False, tiles=None,
+                 stream: Optional[int] = None):
         d = LatticeDesc()
         for k in range(3):
             d.dims[k] = int(dims[k])
@@ -203,6 +206,8 @@ class Lattice:
         d.precision = VD_FP64 if precision == "fp64" else VD_FP32_FP64RED
         d.flags = ((VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
                    | (VD_FLAG_PROFILE if profile else 0))
+        for k in range(VD_MAX_LEVELS):
+            d.tile[k] = int(tiles[k]) if tiles is not None and k < len(tiles) else 0
         self.desc = d
         self.stream = _current_stream() if stream is None else int(stream)
         h = C.c_void_p()
@@ -276,6 +281,16 @@ class Lattice:
                             if r.prof_n[k] > 0},
                 "prof_n": {PROF_NAMES[k]: int(r.prof_n[k]) for k in range(len(PROF_NAMES))
                            if r.prof_n[k] > 0}}
+
+    def tune(self, iters: int = 10):
+        """Run the library's tile autotuner; returns (tiles per level, mean us per
+        CG iteration [level][kind])."""
+        tiles = (C.c_int32 * VD_MAX_LEVELS)()
+        us = (C.c_double * (3 * VD_MAX_LEVELS))()
+        _check(_lib.vd_tune(self._h, int(iters), tiles, us), "vd_tune")
+        n = self.num_levels
+        return ([int(tiles[k]) for k in range(n)],
+                [[float(us[3 * k + j]) for j in range(3)] for k in range(n)])
 
     def get_energy(self) -> np.ndarray:
         out = (C.c_double * 4)()

@@ -69,23 +69,29 @@ struct LevelData {
   T *d = nullptr, *r = nullptr, *pa = nullptr, *pb = nullptr, *ap = nullptr, *dinv = nullptr,
     *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
+  int* node_slot = nullptr;  // node -> row of A27 (-1: no data term)
+  T* A27 = nullptr;          // [27*6][N] data blocks of A, per node slot
   Scalars* sc = nullptr;
-  double* prz[2] = {nullptr, nullptr};  // r^T D^-1 r block partials, alternating
-  double* ppap = nullptr;               // p^T A p block partials
+  T* r2 = nullptr;                      // second CG residual buffer (ping-pong with r)
+  T* ap2 = nullptr;                     // second A p buffer (ping-pong with ap)
+  double* scg[2] = {nullptr, nullptr};  // CG block partials [4][ntiles], alternating
   double* pe = nullptr;                 // energy block partials [3][energy blocks]
   int cap_pe = 0;                       // doubles in pe
   // constraint rows and cell cache
   int cap_rows = 0, cap_cells = 0;
   int *row_cell = nullptr, *sorted = nullptr, *seg_start = nullptr, *active_cell = nullptr;
   T *row_f = nullptr, *row_sn = nullptr, *row_rho = nullptr, *K = nullptr, *bcell = nullptr;
-  int ntiles = 0;
+  int ntiles = 0;     // workgroups of the current tile kind
+  int max_tiles = 0;  // most workgroups over all tile kinds (partials capacity)
+  int tile = 0;       // tile kind of the stencil / CG kernels
 
   LevelView<T> view(double wr) const {
     LevelView<T> v;
-    v.nx = nx; v.ny = ny; v.nz = nz; v.N = N;
+    v.nx = nx; v.ny = ny; v.nz = nz; v.N = N; v.tile = tile;
     v.h = (T)h; v.wr = (T)wr;
     v.d = d; v.r = r; v.ap = ap; v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
     v.cell_map = cell_map; v.K = K; v.sc = sc;
+    v.node_slot = node_slot; v.A27 = A27; v.capA = N;
     return v;
   }
   RowView<T> rows_view(int rows, int n_dense) const {
@@ -122,6 +128,7 @@ class ISolver {
   virtual int debug_rotations(int level, const float* pos, const float* rot_prev, float* rot_out,
                               int mem) = 0;
   virtual int debug_prolong(int level, const float* coarse, float* out, int mem) = 0;
+  virtual int tune(int iters, int* tile_out, double* us_out) = 0;
 };
 
 template <typename T>
@@ -152,7 +159,12 @@ class Solver final : public ISolver {
       v.N = (int)N;
       v.h = h;
       v.ncell = (v.nx - 1) * (v.ny - 1) * (v.nz - 1);
-      v.ntiles = ((v.nx + kTX - 1) / kTX) * ((v.ny + kTY - 1) / kTY) * ((v.nz + kTZ - 1) / kTZ);
+      const int want = desc_.tile[l];
+      if (want < 0 || want > kTileKinds) return VD_EINVAL;
+      v.tile = want > 0 ? want - 1 : default_tile(v.nx, v.ny, v.nz);
+      v.ntiles = tile_blocks(v.tile, v.nx, v.ny, v.nz);
+      for (int k = 0; k < kTileKinds; ++k)
+        v.max_tiles = std::max(v.max_tiles, tile_blocks(k, v.nx, v.ny, v.nz));
       for (int k = 0; k < 3; ++k) dims[k] = (dims[k] + 1) / 2;
       h *= 2.0;
     }
@@ -169,14 +181,18 @@ class Solver final : public ISolver {
       VD_CHECK(pool_.alloc(&v.base, 3 * N));
       VD_CHECK(pool_.alloc(&v.rot, 9 * N));
       VD_CHECK(pool_.alloc(&v.cell_map, (size_t)v.ncell));
+      VD_CHECK(pool_.alloc(&v.node_slot, N));
+      VD_CHECK(pool_.alloc(&v.A27, 162 * N));
       VD_CHECK(pool_.alloc(&v.sc, 1));
       VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
-      const int nrz = std::max(v.ntiles, update_blocks(v.N));
-      VD_CHECK(pool_.alloc(&v.prz[0], (size_t)nrz));
-      VD_CHECK(pool_.alloc(&v.prz[1], (size_t)nrz));
-      VD_CHECK(pool_.alloc(&v.ppap, (size_t)v.ntiles));
+      VD_CHECK(pool_.alloc(&v.r2, 3 * N));
+      VD_CHECK(pool_.alloc(&v.ap2, 3 * N));
+      VD_CHECK(pool_.alloc(&v.scg[0], 4 * (size_t)v.max_tiles));
+      VD_CHECK(pool_.alloc(&v.scg[1], 4 * (size_t)v.max_tiles));
       VD_CHECK(ensure_partials(v, 0));
     }
+    VD_CHECK(pool_.alloc(&node_flags_, (size_t)finest().N));
+    VD_CHECK(pool_.alloc(&node_scan_, (size_t)finest().N));
     VD_CHECK(pool_.alloc(&d_flags_, 4));
     VD_TRY(hipHostMalloc((void**)&h_flags_, 4 * sizeof(int), hipHostMallocDefault));
     VD_TRY(hipHostMalloc((void**)&h_sc_, sizeof(Scalars), hipHostMallocDefault));
@@ -236,7 +252,10 @@ class Solver final : public ISolver {
       VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, heads_, scan_, rows, stream_));
       VD_TRY(launch_segments<T>(V, R, keys_out_, scan_, v.cell_map, v.ncell, stream_));
       VD_TRY(launch_build_cells<T>(V, R, v.K, std::min(v.cap_cells, 8192), stream_));
-      VD_TRY(launch_assemble_nodes<T>(V, R, stream_));
+      VD_TRY(launch_node_flags<T>(V, node_flags_, stream_));
+      VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, node_flags_, node_scan_, v.N, stream_));
+      VD_TRY(launch_assemble_nodes<T>(V, R, node_flags_, node_scan_, v.node_slot, v.A27,
+                                      stream_));
       VD_TRY(launch_reset_counters(v.sc, rows, C, 1, stream_));
     }
     rows_ = rows;
@@ -366,8 +385,7 @@ class Solver final : public ISolver {
     const int N = v.N;
     VD_CHECK(upload_aos(p, 3 * N, mem));
     VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, N, stream_));
-    VD_TRY(launch_stencil<T>(kModeApply, v.view(desc_.w_arap), dbg_t1_, dbg_t2_, nullptr, nullptr,
-                             Red{}, stream_));
+    VD_TRY(launch_stencil<T>(kModeApply, v.view(desc_.w_arap), dbg_t1_, dbg_t2_, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(ap, 3 * N, mem);
   }
@@ -378,7 +396,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot, mem, &V));
     const int N = V.N;
-    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, nullptr, nullptr, Red{}, stream_));
+    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(g, 3 * N, mem);
   }
@@ -452,6 +470,76 @@ class Solver final : public ISolver {
     return download_aos(out, 3 * f.N, mem);
   }
 
+  // Tile autotuner: times the CG iteration kernel with every tile kind.
+  int tune(int iters, int* tile_out, double* us_out) override {
+    if (!have_constraints_) return VD_ESTATE;
+    if (iters < 1) return VD_EINVAL;
+    const double wr = desc_.w_arap;
+    hipEvent_t e0, e1;
+    VD_TRY(hipEventCreate(&e0));
+    VD_TRY(hipEventCreate(&e1));
+    int rc = VD_OK;
+    for (int l = 0; l < L_ && rc == VD_OK; ++l) {
+      LevelData<T>& v = lv_[l];
+      const size_t N = v.N;
+      T* saved = nullptr;
+      rc = pool_.alloc(&saved, 3 * N);
+      if (rc != VD_OK) break;
+      VD_TRY(hipMemcpyAsync(saved, v.d, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+      double best = 1e300;
+      int best_kind = v.tile;
+      for (int kind = 0; kind < kTileKinds; ++kind) {
+        v.tile = kind;
+        v.ntiles = tile_blocks(kind, v.nx, v.ny, v.nz);
+        const LevelView<T> V = v.view(wr);
+        T* rb[2] = {v.r, v.r2};
+        T* pb[2] = {v.pa, v.pb};
+        T* ab[2] = {v.ap, v.ap2};
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {  // first pass warms up
+          VD_TRY(hipMemcpyAsync(v.d, saved, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+          VD_TRY(launch_stencil<T>(kModeRhs, V, nullptr, nullptr, stream_));
+          VD_TRY(hipEventRecord(e0, stream_));
+          for (int m = 0; m < iters; ++m) {
+            CgIo<T> io{};
+            const int cur = m % 2, prv = (m + 1) % 2;
+            io.r_in = m == 0 ? rb[0] : rb[prv];
+            io.r_out = rb[cur];
+            io.p_in = pb[prv];
+            io.p_out = pb[cur];
+            io.ap_in = ab[prv];
+            io.ap_out = ab[cur];
+            io.s_in = v.scg[prv];
+            io.n_in = v.ntiles;
+            io.s_out = v.scg[cur];
+            VD_TRY(launch_cg<T>(m == 0, V, io, stream_));
+          }
+          VD_TRY(hipEventRecord(e1, stream_));
+          VD_TRY(hipEventSynchronize(e1));
+          VD_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+        const double us = 1000.0 * ms / iters;
+        if (us_out) us_out[3 * l + kind] = us;
+        if (us < best) {
+          best = us;
+          best_kind = kind;
+        }
+      }
+      v.tile = best_kind;
+      v.ntiles = tile_blocks(best_kind, v.nx, v.ny, v.nz);
+      desc_.tile[l] = best_kind + 1;
+      if (tile_out) tile_out[l] = best_kind + 1;
+      VD_TRY(hipMemcpyAsync(v.d, saved, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(saved);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ++alloc_gen_;  // schedules captured with the old tiles are stale
+    energy_fresh_ = false;
+    return rc;
+  }
+
  private:
   LevelData<T>& finest() { return lv_[L_ - 1]; }
 
@@ -481,36 +569,34 @@ class Solver final : public ISolver {
                        [&] { return launch_polar<T>(V, v.d, v.rot, v.rot, s); }));
       }
       const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
-      const int nt = v.ntiles, nu = update_blocks(v.N);
+      // CG iterate m keeps r_m, p_m, Ap_m and its block partials S_m in
+      // buffer m % 2 of each pair (k_cg reads iterate m-1 from the other).
+      T* rb[2] = {v.r, v.r2};
+      T* pb[2] = {v.pa, v.pb};
+      T* ab[2] = {v.ap, v.ap2};
       for (int k = 0; k < gn; ++k) {
-        // r^T D^-1 r of iterate m lives in prz[m % 2]; iterate 0 comes from
-        // the gradient pass (nt partials), later ones from phase B (nu).
-        Red g{};
-        g.out = v.prz[0];
         VD_CHECK(timed(on, VD_PROF_GRADIENT, s, [&] {
-          return launch_stencil<T>(kModeRhs, V, nullptr, nullptr, nullptr, nullptr, g, s);
+          return launch_stencil<T>(kModeRhs, V, nullptr, nullptr, s);
         }));
         for (int m = 0; m < pcg; ++m) {
-          T* p_old = (m % 2 == 0) ? v.pa : v.pb;
-          T* p_new = (m % 2 == 0) ? v.pb : v.pa;
-          Red a{};
-          a.cur = v.prz[m % 2];
-          a.n_cur = m == 0 ? nt : nu;
-          if (m > 0) {
-            a.prev = v.prz[(m - 1) % 2];
-            a.n_prev = m == 1 ? nt : nu;
-          }
-          a.out = v.ppap;
-          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] {
-            return launch_stencil<T>(kModePcg, V, nullptr, nullptr, p_old, p_new, a, s);
+          CgIo<T> io{};
+          const int cur = m % 2, prv = (m + 1) % 2;
+          io.r_in = m == 0 ? rb[0] : rb[prv];
+          io.r_out = rb[cur];
+          io.p_in = pb[prv];
+          io.p_out = pb[cur];
+          io.ap_in = ab[prv];
+          io.ap_out = ab[cur];
+          io.s_in = v.scg[prv];
+          io.n_in = v.ntiles;
+          io.s_out = v.scg[cur];
+          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] { return launch_cg<T>(m == 0, V, io, s); }));
+        }
+        if (pcg > 0) {
+          const int last = (pcg - 1) % 2;
+          VD_CHECK(timed(on, VD_PROF_CG_B, s, [&] {
+            return launch_cg_final<T>(V, pb[last], v.scg[last], v.ntiles, s);
           }));
-          Red b{};
-          b.cur = v.prz[m % 2];
-          b.n_cur = m == 0 ? nt : nu;
-          b.pap = v.ppap;
-          b.n_pap = nt;
-          b.out = v.prz[(m + 1) % 2];
-          VD_CHECK(timed(on, VD_PROF_CG_B, s, [&] { return launch_update<T>(V, p_new, b, s); }));
         }
         if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, v.pe, 1, s));
         VD_CHECK(timed(on, VD_PROF_ROTATION, s,
@@ -614,7 +700,8 @@ class Solver final : public ISolver {
       VD_CHECK(pool_.alloc(&vals_in_, cap));
       VD_CHECK(pool_.alloc(&heads_, cap));
       VD_CHECK(pool_.alloc(&scan_, cap));
-      sort_temp_bytes_ = std::max(vd::sort_temp_bytes(cap), vd::scan_temp_bytes(cap));
+      sort_temp_bytes_ = std::max({vd::sort_temp_bytes(cap), vd::scan_temp_bytes(cap),
+                                   vd::scan_temp_bytes(finest().N)});
       VD_CHECK(pool_.alloc((unsigned char**)&sort_temp_, sort_temp_bytes_));
       cap_rows_ = cap;
       ++alloc_gen_;
@@ -704,6 +791,8 @@ class Solver final : public ISolver {
   Pool pool_;
   int* d_flags_ = nullptr;
   int* h_flags_ = nullptr;
+  int* node_flags_ = nullptr;  // per-node scratch of the constraint build
+  int* node_scan_ = nullptr;
   Scalars* h_sc_ = nullptr;
   // staging of the raw constraints
   float *st_canon_ = nullptr, *st_target_ = nullptr, *st_normal_ = nullptr, *st_weight_ = nullptr,
@@ -763,6 +852,8 @@ int vd_lattice_create(const vd_lattice_desc* d, void* stream, vd_lattice** out) 
       if (dims[k] < 2) return VD_EINVAL;
   }
   if (d->precision != VD_FP32_FP64RED && d->precision != VD_FP64) return VD_EINVAL;
+  for (int l = 0; l < VD_MAX_LEVELS; ++l)
+    if (d->tile[l] < 0 || d->tile[l] > vd::kTileKinds) return VD_EINVAL;
   vd::ISolver* impl = nullptr;
   if (d->precision == VD_FP64)
     impl = new (std::nothrow) vd::Solver<double>(*d, (hipStream_t)stream);
@@ -831,6 +922,11 @@ const char* vd_strerror(int code) {
     case VD_ESTATE: return "call not valid in the current state (no constraints set?)";
     default: return "unknown status code";
   }
+}
+
+int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out) {
+  if (!l) return VD_EINVAL;
+  return l->impl->tune(iters, tile_out, us_out);
 }
 
 int vd_debug_apply(vd_lattice* l, int32_t level, const float* p, float* Ap, int32_t mem) {

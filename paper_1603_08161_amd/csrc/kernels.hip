@@ -220,10 +220,16 @@ hipError_t launch_segments(const LevelView<T>& L, const RowView<T>& R, const uns
 // B^T B and B^T b cached per active cell (Sec. 7.1: "pre-compute and cache").
 // Block for corners (a, b): sum over the cell's rows of
 // alpha_a alpha_b sn sn^T (symmetric 3x3); rhs block of corner a:
-// sum alpha_a sn rho.  One workgroup per cell, one output entry per thread,
-// rows visited in sorted order (deterministic, float64 accumulation).
+// sum alpha_a sn rho.  One workgroup per cell; rows are staged through LDS
+// in chunks of 256 (corner weights computed once per row); each thread owns
+// one output entry and accumulates it in float64 over the rows in sorted
+// order (deterministic).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_build_cells(RowView<T> R, T* K, const Scalars* sc) {
+  constexpr int P = kBlock + 1;  // padded rows: conflict-free column reads
+  __shared__ T s_w[8 * P];
+  __shared__ T s_sn[3 * P];
+  __shared__ T s_rho[kBlock];
   const int n_active = sc->n_active;
   const int rows = R.rows;
   const int j = threadIdx.x;
@@ -243,27 +249,55 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(RowView<T> R, T* K, cons
   for (int a = blockIdx.x; a < n_active; a += gridDim.x) {
     const int s0 = R.seg_start[a], s1 = R.seg_start[a + 1];
     double acc = 0.0;
-    if (kind < 2) {
-      for (int s = s0; s < s1; ++s) {
-        const int row = R.sorted[s];
+    for (int base = s0; base < s1; base += kBlock) {
+      const int cnt = min(kBlock, s1 - base);
+      __syncthreads();
+      if (j < cnt) {
+        const int row = R.sorted[base + j];
         const T fx = R.f[row], fy = R.f[(size_t)rows + row], fz = R.f[2 * (size_t)rows + row];
-        const T sni = R.sn[(size_t)ci * rows + row];
-        const double wa = (double)corner_weight<T>(ca, fx, fy, fz);
-        if (kind == 0) {
-          const T snj = R.sn[(size_t)cj * rows + row];
-          const double wb = (double)corner_weight<T>(cb, fx, fy, fz);
-          acc += wa * wb * (double)sni * (double)snj;
-        } else {
-          acc += wa * (double)sni * (double)R.rho[row];
-        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s_w[k * P + j] = corner_weight<T>(k, fx, fy, fz);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_sn[k * P + j] = R.sn[(size_t)k * rows + row];
+        s_rho[j] = R.rho[row];
       }
+      __syncthreads();
+      // four independent accumulators keep several LDS reads in flight
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (kind == 0) {
-        const int comp = j % 6;
-        K[((size_t)a * 64 + ca * 8 + cb) * 6 + comp] = (T)acc;
-        if (ca != cb) K[((size_t)a * 64 + cb * 8 + ca) * 6 + comp] = (T)acc;
-      } else {
-        R.bcell[((size_t)a * 8 + ca) * 3 + ci] = (T)acc;
+        auto term = [&](int q) {
+          return (double)s_w[ca * P + q] * (double)s_w[cb * P + q] *
+                 ((double)s_sn[ci * P + q] * (double)s_sn[cj * P + q]);
+        };
+        int q = 0;
+        for (; q + 4 <= cnt; q += 4) {
+          a0 += term(q);
+          a1 += term(q + 1);
+          a2 += term(q + 2);
+          a3 += term(q + 3);
+        }
+        for (; q < cnt; ++q) a0 += term(q);
+      } else if (kind == 1) {
+        auto term = [&](int q) {
+          return (double)s_w[ca * P + q] * ((double)s_sn[ci * P + q] * (double)s_rho[q]);
+        };
+        int q = 0;
+        for (; q + 4 <= cnt; q += 4) {
+          a0 += term(q);
+          a1 += term(q + 1);
+          a2 += term(q + 2);
+          a3 += term(q + 3);
+        }
+        for (; q < cnt; ++q) a0 += term(q);
       }
+      acc += (a0 + a1) + (a2 + a3);
+    }
+    if (kind == 0) {
+      const int comp = j % 6;
+      K[((size_t)a * 64 + ca * 8 + cb) * 6 + comp] = (T)acc;
+      if (ca != cb) K[((size_t)a * 64 + cb * 8 + ca) * 6 + comp] = (T)acc;
+    } else if (kind == 1) {
+      R.bcell[((size_t)a * 8 + ca) * 3 + ci] = (T)acc;
     }
   }
 }
@@ -276,41 +310,97 @@ hipError_t launch_build_cells(const LevelView<T>& L, const RowView<T>& R, T* K, 
   return hipGetLastError();
 }
 
-// Per node: Jacobi diagonal diag(A) = 2 w_r |N_i| + data diagonal, and the
-// data right-hand side b_i, both gathered from the adjacent cells.
+// flags[i] = 1 when node i is a corner of at least one active cell.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R) {
+__global__ __launch_bounds__(kBlock) void k_node_flags(LevelView<T> L, int* flags) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const int cnx = L.nx - 1, cny = L.ny - 1, cnz = L.nz - 1;
+  int f = 0;
+  for (int a = 0; a < 8; ++a) {
+    const int cx = x - (a & 1), cy = y - ((a >> 1) & 1), cz = z - (a >> 2);
+    if (in_box(cx, cy, cz, cnx, cny, cnz) && L.cell_map[cx + cnx * (cy + cny * cz)] >= 0) f = 1;
+  }
+  flags[i] = f;
+}
+
+template <typename T>
+hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
+  k_node_flags<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, flags);
+  return hipGetLastError();
+}
+
+// Per node: the data part of row i of A as a 27-point block stencil,
+// A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
+// = corner b, delta = b - a) of K_c[a][b]; stored SoA [27*6][capA] at the
+// node's compact slot.  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
+// and the data right-hand side b_i gathered from the cells.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R,
+                                                           const int* flags, const int* scan,
+                                                           int* node_slot, T* A27) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.N) return;
   const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
   const int nb = (x > 0) + (x < L.nx - 1) + (y > 0) + (y < L.ny - 1) + (z > 0) + (z < L.nz - 1);
-  T dg[3] = {T(2) * L.wr * T(nb), T(2) * L.wr * T(nb), T(2) * L.wr * T(nb)};
-  T b[3] = {0, 0, 0};
   const int cnx = L.nx - 1, cny = L.ny - 1, cnz = L.nz - 1;
+  int cells[8];
+#pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int cx = x - (a & 1), cy = y - ((a >> 1) & 1), cz = z - (a >> 2);
-    if (!in_box(cx, cy, cz, cnx, cny, cnz)) continue;
-    const int ci = L.cell_map[cx + cnx * (cy + cny * cz)];
-    if (ci < 0) continue;
-    const T* blk = L.K + ((size_t)ci * 64 + a * 8 + a) * 6;
-    dg[0] += blk[0];
-    dg[1] += blk[3];
-    dg[2] += blk[5];
-    const T* bc = R.bcell + ((size_t)ci * 8 + a) * 3;
-    b[0] += bc[0];
-    b[1] += bc[1];
-    b[2] += bc[2];
+    cells[a] = in_box(cx, cy, cz, cnx, cny, cnz) ? L.cell_map[cx + cnx * (cy + cny * cz)] : -1;
+  }
+  const int slot = flags[i] ? scan[i] : -1;
+  node_slot[i] = slot;
+  T dg[3] = {T(0), T(0), T(0)};
+  T b[3] = {T(0), T(0), T(0)};
+  if (slot >= 0) {
+    // each adjacent cell's block row K_c[a][*] is read once and scattered
+    // into the 27 offsets delta = b - a (summed over a in ascending order)
+    T acc[27][6];
+#pragma unroll
+    for (int dl = 0; dl < 27; ++dl)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[dl][k] = T(0);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (cells[a] < 0) continue;
+      const T* __restrict__ row = L.K + ((size_t)cells[a] * 64 + a * 8) * 6;
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb) {
+        const int dl = ((bb & 1) - (a & 1) + 1) + 3 * ((((bb >> 1) & 1) - ((a >> 1) & 1) + 1) +
+                                                      3 * ((bb >> 2) - (a >> 2) + 1));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[dl][k] += row[bb * 6 + k];
+      }
+      const T* bc = R.bcell + ((size_t)cells[a] * 8 + a) * 3;
+      b[0] += bc[0];
+      b[1] += bc[1];
+      b[2] += bc[2];
+    }
+    const size_t cap = L.capA;
+#pragma unroll
+    for (int dl = 0; dl < 27; ++dl)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) A27[(size_t)(dl * 6 + k) * cap + slot] = acc[dl][k];
+    dg[0] = acc[13][0];
+    dg[1] = acc[13][3];
+    dg[2] = acc[13][5];
   }
   const size_t N = L.N;
+  const T arap = T(2) * L.wr * T(nb);
   for (int k = 0; k < 3; ++k) {
-    L.dinv[k * N + i] = dg[k] > T(0) ? T(1) / dg[k] : T(0);
+    const T dk = arap + dg[k];
+    L.dinv[k * N + i] = dk > T(0) ? T(1) / dk : T(0);
     L.bnode[k * N + i] = b[k];
   }
 }
 
 template <typename T>
-hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hipStream_t s) {
-  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R);
+hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
+                                 const int* scan, int* node_slot, T* A27, hipStream_t s) {
+  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R, flags, scan, node_slot, A27);
   return hipGetLastError();
 }
 
@@ -319,231 +409,190 @@ hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hip
 // ===========================================================================
 //
 // A p at node i = 2 w_r sum_{j in N_i} (p_i - p_j)                (ARAP part)
-//               + sum_{adjacent cells c, i = corner a of c}
-//                   sum_{corners b} K_c[a][b] p_{corner b}        (data part)
+//               + sum_{delta in {-1,0,1}^3} A27_i[delta] p_{i+delta}  (data part)
 //
-// One workgroup per 8x8x4 tile; the tile plus a one-node halo of p is staged
-// in LDS (all 27 stencil neighbours of a tile node are in it).
-//
-// kModePcg : beta = rz_cur / rz_prev from the previous kernels' partials;
-//            p = D^-1 r + beta p_old (p = D^-1 r on the first iteration) is
-//            formed while staging and written to p_new; A p is written and
-//            the block partials of p^T A p go to red.out.
-// kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
-//            gradient J^T r; r = -g is stored and the partials of
-//            r^T D^-1 r go to red.out.
-// kModeApply / kModeGrad : A p or g written to `out` (test entry points).
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __restrict__ pin,
-                                                    T* __restrict__ out,
-                                                    const T* __restrict__ p_old,
-                                                    T* __restrict__ p_new, Red red) {
-  __shared__ T sp[3][kHalo];
-  const int ntx = (L.nx + kTX - 1) / kTX, nty = (L.ny + kTY - 1) / kTY;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-  const int x0 = tx * kTX - 1, y0 = ty * kTY - 1, z0 = tz * kTZ - 1;
-  const size_t N = L.N;
+// One workgroup per tile; the tile plus a one-node halo of p is staged in LDS
+// (all 27 stencil neighbours of a tile node are in it; nodes outside the
+// lattice hold 0 and have zero blocks).  Levels with enough nodes to give
+// >= 256 wide tiles use TileW (32x8x4, 4 nodes per thread), others TileS.
 
-  T beta = T(0);
-  bool first = true;
-  if (MODE == kModePcg) {
-    first = (red.prev == nullptr);
-    if (!first) {
-      const double rz_cur = sum_partials(red.cur, red.n_cur);
-      const double rz_prev = sum_partials(red.prev, red.n_prev);
-      beta = rz_prev > 0.0 ? (T)(rz_cur / rz_prev) : T(0);
+int tile_blocks(int kind, int nx, int ny, int nz) {
+  auto nb = [&](int tx, int ty, int tz) {
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+  };
+  switch (kind) {
+    case 1: return nb(TileM::TX, TileM::TY, TileM::TZ);
+    case 2: return nb(TileW::TX, TileW::TY, TileW::TZ);
+    default: return nb(TileS::TX, TileS::TY, TileS::TZ);
+  }
+}
+
+int default_tile(int nx, int ny, int nz) {
+  return tile_blocks(1, nx, ny, nz) >= 512 ? 1 : 0;
+}
+
+int update_blocks(int N) { return blocks_for(N); }
+int energy_blocks(int cap_rows, int N) { return blocks_for(cap_rows) + blocks_for(N); }
+
+template <typename TL>
+struct TilePos {
+  int x0, y0, z0;  // lattice coordinates of LDS index (0,0,0) (tile origin - 1)
+  __device__ __forceinline__ TilePos(int nx, int ny) {
+    const int ntx = (nx + TL::TX - 1) / TL::TX, nty = (ny + TL::TY - 1) / TL::TY;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    x0 = tx * TL::TX - 1;
+    y0 = ty * TL::TY - 1;
+    z0 = tz * TL::TZ - 1;
+  }
+  // LDS index of the k-th node owned by this thread
+  __device__ __forceinline__ static int own(int k) {
+    const int t = threadIdx.x;
+    const int lx = t % TL::TX + 1, ly = (t / TL::TX) % TL::TY + 1;
+    const int lz = (t / (TL::TX * TL::TY)) * TL::NPT + k + 1;
+    return lx + TL::HX * (ly + TL::HY * lz);
+  }
+};
+
+// A p at the tile node with LDS index c and lattice coordinates (gx,gy,gz).
+template <typename T, typename TL>
+__device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
+                                         int gx, int gy, int gz, size_t i, T& o0, T& o1,
+                                         T& o2) {
+  const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
+  T l0 = T(0), l1 = T(0), l2 = T(0);
+  const int off[3] = {1, TL::HX, TL::HX * TL::HY};
+  const int pos[3] = {gx, gy, gz};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (pos[ax] > 0) {
+      const int q = c - off[ax];
+      l0 += p0 - sp[0][q];
+      l1 += p1 - sp[1][q];
+      l2 += p2 - sp[2][q];
+    }
+    if (pos[ax] < lim[ax] - 1) {
+      const int q = c + off[ax];
+      l0 += p0 - sp[0][q];
+      l1 += p1 - sp[1][q];
+      l2 += p2 - sp[2][q];
     }
   }
-  const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
-  const T* __restrict__ r = L.r;
-  const T* __restrict__ dinv = L.dinv;
+  const T w2 = T(2) * L.wr;
+  o0 = w2 * l0;
+  o1 = w2 * l1;
+  o2 = w2 * l2;
+  const int slot = L.node_slot[i];
+  if (slot >= 0) {
+    const size_t cap = L.capA;
+    const T* __restrict__ A = L.A27 + slot;
+#pragma unroll
+    for (int dl = 0; dl < 27; ++dl) {
+      const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
+      const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
+      const T* __restrict__ blk = A + (size_t)dl * 6 * cap;
+      const T s0 = blk[0], s1 = blk[cap], s2 = blk[2 * cap], s3 = blk[3 * cap],
+              s4 = blk[4 * cap], s5 = blk[5 * cap];
+      const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
+      o0 += s0 * q0 + s1 * q1 + s2 * q2;
+      o1 += s1 * q0 + s3 * q1 + s4 * q2;
+      o2 += s2 * q0 + s4 * q1 + s5 * q2;
+    }
+  }
+}
 
-  for (int k = threadIdx.x; k < kHalo; k += kBlock) {
-    const int lx = k % kHX, ly = (k / kHX) % kHY, lz = k / (kHX * kHY);
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+// kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
+//            gradient J^T r; r = -g is stored (the CG residual r_0).
+// kModeApply / kModeGrad : A p or g written to `out` (test entry points).
+template <typename T, typename TL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(LevelView<T> L, const T* __restrict__ pin,
+                                                    T* __restrict__ out) {
+  __shared__ T sp[3][TL::HALO];
+  const TilePos<TL> t(L.nx, L.ny);
+  const size_t N = L.N;
+  const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
+  for (int k = threadIdx.x; k < TL::HALO; k += kBlock) {
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     T v0 = T(0), v1 = T(0), v2 = T(0);
     if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
-      if (MODE == kModePcg) {
-        const T r0 = r[i], r1 = r[N + i], r2 = r[2 * N + i];
-        const T q0 = dinv[i], q1 = dinv[N + i], q2 = dinv[2 * N + i];
-        v0 = q0 * r0;
-        v1 = q1 * r1;
-        v2 = q2 * r2;
-        if (!first) {
-          v0 += beta * p_old[i];
-          v1 += beta * p_old[N + i];
-          v2 += beta * p_old[2 * N + i];
-        }
-        if (lx >= 1 && lx <= kTX && ly >= 1 && ly <= kTY && lz >= 1 && lz <= kTZ) {
-          p_new[i] = v0;
-          p_new[N + i] = v1;
-          p_new[2 * N + i] = v2;
-        }
-      } else {
-        v0 = src[i];
-        v1 = src[N + i];
-        v2 = src[2 * N + i];
-      }
+      v0 = src[i];
+      v1 = src[N + i];
+      v2 = src[2 * N + i];
     }
     sp[0][k] = v0;
     sp[1][k] = v1;
     sp[2][k] = v2;
   }
   __syncthreads();
-
-  const int lx = threadIdx.x % kTX + 1, ly = (threadIdx.x / kTX) % kTY + 1,
-            lz = threadIdx.x / (kTX * kTY) + 1;
-  const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-  const bool valid = in_box(gx, gy, gz, L.nx, L.ny, L.nz);
-  const int c = lx + kHX * (ly + kHY * lz);
-  T o0 = T(0), o1 = T(0), o2 = T(0);
-  const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
-  size_t i = 0;
-  if (valid) {
-    i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
-    // ARAP Laplacian
-    T l0 = T(0), l1 = T(0), l2 = T(0);
-    const int off[3] = {1, kHX, kHX * kHY};
-    const int pos[3] = {gx, gy, gz};
-    const int lim[3] = {L.nx, L.ny, L.nz};
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      if (pos[ax] > 0) {
-        const int q = c - off[ax];
-        l0 += p0 - sp[0][q];
-        l1 += p1 - sp[1][q];
-        l2 += p2 - sp[2][q];
-      }
-      if (pos[ax] < lim[ax] - 1) {
-        const int q = c + off[ax];
-        l0 += p0 - sp[0][q];
-        l1 += p1 - sp[1][q];
-        l2 += p2 - sp[2][q];
-      }
-    }
-    const T w2 = T(2) * L.wr;
-    o0 = w2 * l0;
-    o1 = w2 * l1;
-    o2 = w2 * l2;
-    // data term from the cached cell blocks
-    const int cnx = L.nx - 1, cny = L.ny - 1, cnz = L.nz - 1;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int dx = a & 1, dy = (a >> 1) & 1, dz = a >> 2;
-      const int cx = gx - dx, cy = gy - dy, cz = gz - dz;
-      if (!in_box(cx, cy, cz, cnx, cny, cnz)) continue;
-      const int ci = L.cell_map[cx + cnx * (cy + cny * cz)];
-      if (ci < 0) continue;
-      const T* __restrict__ kr = L.K + ((size_t)ci * 64 + a * 8) * 6;
-      const int cb0 = c - dx - kHX * (dy + kHY * dz);  // local index of the cell's corner 0
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int q = cb0 + (b & 1) + kHX * (((b >> 1) & 1) + kHY * (b >> 2));
-        sym3_madd<T>(kr + b * 6, sp[0][q], sp[1][q], sp[2][q], o0, o1, o2);
-      }
-    }
-  }
-
-  if (MODE == kModeApply) {
-    if (valid) {
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    T o0, o1, o2;
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o0, o1, o2);
+    if (MODE == kModeApply) {
       out[i] = o0;
       out[N + i] = o1;
       out[2 * N + i] = o2;
+      continue;
     }
-    return;
-  }
-  if (MODE == kModeRhs || MODE == kModeGrad) {
-    T g0 = T(0), g1 = T(0), g2 = T(0);
-    if (valid) {
-      // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
-      // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
-      const T* __restrict__ rot = L.rot;
-      T q0 = T(0), q1 = T(0), q2 = T(0);
-      const int pos[3] = {gx, gy, gz};
-      const int lim[3] = {L.nx, L.ny, L.nz};
-      const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+    // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
+    // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
+    const T* __restrict__ rot = L.rot;
+    T q0 = T(0), q1 = T(0), q2 = T(0);
+    const int pos[3] = {gx, gy, gz};
+    const int lim[3] = {L.nx, L.ny, L.nz};
+    const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const T ci0 = rot[rot_at(0, ax, N, i)], ci1 = rot[rot_at(1, ax, N, i)],
-                ci2 = rot[rot_at(2, ax, N, i)];
+    for (int ax = 0; ax < 3; ++ax) {
+      const T ci0 = rot[rot_at(0, ax, N, i)], ci1 = rot[rot_at(1, ax, N, i)],
+              ci2 = rot[rot_at(2, ax, N, i)];
 #pragma unroll
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-          const int pj = pos[ax] + sgn;
-          if (pj < 0 || pj >= lim[ax]) continue;
-          const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
-          const T cj0 = rot[rot_at(0, ax, N, j)], cj1 = rot[rot_at(1, ax, N, j)],
-                  cj2 = rot[rot_at(2, ax, N, j)];
-          const T s = -T(sgn) * L.h;
-          T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
-          if (ax == 0) u0 += T(2);
-          if (ax == 1) u1 += T(2);
-          if (ax == 2) u2 += T(2);
-          q0 += s * u0;
-          q1 += s * u1;
-          q2 += s * u2;
-        }
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const int pj = pos[ax] + sgn;
+        if (pj < 0 || pj >= lim[ax]) continue;
+        const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+        const T cj0 = rot[rot_at(0, ax, N, j)], cj1 = rot[rot_at(1, ax, N, j)],
+                cj2 = rot[rot_at(2, ax, N, j)];
+        const T s = -T(sgn) * L.h;
+        T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
+        if (ax == 0) u0 += T(2);
+        if (ax == 1) u1 += T(2);
+        if (ax == 2) u2 += T(2);
+        q0 += s * u0;
+        q1 += s * u1;
+        q2 += s * u2;
       }
-      g0 = o0 - L.bnode[i] + L.wr * q0;
-      g1 = o1 - L.bnode[N + i] + L.wr * q1;
-      g2 = o2 - L.bnode[2 * N + i] + L.wr * q2;
     }
-    if (MODE == kModeGrad) {
-      if (valid) {
-        out[i] = g0;
-        out[N + i] = g1;
-        out[2 * N + i] = g2;
-      }
-      return;
-    }
-    double part[1] = {0.0};
-    if (valid) {
-      const T r0 = -g0, r1 = -g1, r2 = -g2;
-      T* __restrict__ rw = L.r;
-      rw[i] = r0;
-      rw[N + i] = r1;
-      rw[2 * N + i] = r2;
-      part[0] = (double)(r0 * dinv[i]) * (double)r0 + (double)(r1 * dinv[N + i]) * (double)r1 +
-                (double)(r2 * dinv[2 * N + i]) * (double)r2;
-    }
-    write_block_partials<1>(part, red.out, 0);
-    return;
+    const T g0 = o0 - L.bnode[i] + L.wr * q0;
+    const T g1 = o1 - L.bnode[N + i] + L.wr * q1;
+    const T g2 = o2 - L.bnode[2 * N + i] + L.wr * q2;
+    T* __restrict__ dst = (MODE == kModeGrad) ? out : L.r;
+    const T sg = (MODE == kModeGrad) ? T(1) : T(-1);
+    dst[i] = sg * g0;
+    dst[N + i] = sg * g1;
+    dst[2 * N + i] = sg * g2;
   }
-  // kModePcg
-  double part[1] = {0.0};
-  if (valid) {
-    T* __restrict__ ap = L.ap;
-    ap[i] = o0;
-    ap[N + i] = o1;
-    ap[2 * N + i] = o2;
-    part[0] = (double)p0 * (double)o0 + (double)p1 * (double)o1 + (double)p2 * (double)o2;
-  }
-  write_block_partials<1>(part, red.out, 0);
 }
 
-int stencil_blocks(int nx, int ny, int nz) {
-  return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kTZ - 1) / kTZ);
-}
-int update_blocks(int N) { return blocks_for(N); }
-int energy_blocks(int cap_rows, int N) { return blocks_for(cap_rows) + blocks_for(N); }
-
-template <typename T>
-hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
-                          T* p_new, const Red& red, hipStream_t s) {
-  const int grid = stencil_blocks(L.nx, L.ny, L.nz);
+template <typename T, typename TL>
+hipError_t launch_stencil_t(int mode, const LevelView<T>& L, const T* pin, T* out, hipStream_t s) {
+  const int grid = tile_blocks(L.tile, L.nx, L.ny, L.nz);
   switch (mode) {
-    case kModePcg:
-      k_stencil<T, kModePcg><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
-      break;
     case kModeRhs:
-      k_stencil<T, kModeRhs><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
+      k_stencil<T, TL, kModeRhs><<<grid, kBlock, 0, s>>>(L, pin, out);
       break;
     case kModeApply:
-      k_stencil<T, kModeApply><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
+      k_stencil<T, TL, kModeApply><<<grid, kBlock, 0, s>>>(L, pin, out);
       break;
     case kModeGrad:
-      k_stencil<T, kModeGrad><<<grid, kBlock, 0, s>>>(L, pin, out, p_old, p_new, red);
+      k_stencil<T, TL, kModeGrad><<<grid, kBlock, 0, s>>>(L, pin, out);
       break;
     default:
       return hipErrorInvalidValue;
@@ -551,53 +600,184 @@ hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, hipStream_t s) {
+  switch (L.tile) {
+    case 1: return launch_stencil_t<T, TileM>(mode, L, pin, out, s);
+    case 2: return launch_stencil_t<T, TileW>(mode, L, pin, out, s);
+    default: return launch_stencil_t<T, TileS>(mode, L, pin, out, s);
+  }
+}
+
 // ===========================================================================
-// CG phase B: alpha = rz / p^T A p; d += alpha p; r -= alpha A p;
-// partials of the new r^T D^-1 r
+// one Jacobi-preconditioned CG iteration per launch (Sec. 7.1, position step)
 // ===========================================================================
+//
+// Iteration m (FIRST: m = 0) reads the block partials S_{m-1} of the
+// previous launch: r^T D^-1 r, p^T A p, (Ap)^T D^-1 r and (Ap)^T D^-1 Ap of
+// iterate m-1.  From them
+//   alpha_{m-1} = rz_{m-1} / p^T A p                    (zero if p^T A p <= 0)
+//   rz_m        = rz_{m-1} - 2 alpha (Ap)^T D^-1 r + alpha^2 (Ap)^T D^-1 Ap
+//   beta_m      = rz_m / rz_{m-1}                       (zero if rz_{m-1} <= 0)
+// (rz_m is r_m^T D^-1 r_m expanded through r_m = r_{m-1} - alpha Ap_{m-1}, so
+// one reduction phase per iteration suffices).  While staging the tile it
+// forms r_m = r_{m-1} - alpha Ap_{m-1}, p_m = D^-1 r_m + beta p_{m-1}, applies
+// d += alpha p_{m-1} to its own nodes, computes Ap_m and writes S_m.  The
+// last iteration's step is applied by k_cg_final.  The halo inputs are
+// loaded before the scalar reduction so that both latencies overlap.
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(LevelView<T> L, const T* __restrict__ p,
-                                                   Red red) {
-  const double pap = sum_partials(red.pap, red.n_pap);
-  const double rz = sum_partials(red.cur, red.n_cur);
-  const T alpha = pap > 0.0 ? (T)(rz / pap) : T(0);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !(pap > 0.0)) L.sc->guard_hits += 1;
+__device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& beta,
+                                           Scalars* sc) {
+  double v[4];
+  sum_partials_k<4>(s, n, v);
+  const double rz = v[0], pap = v[1], apdr = v[2], apdap = v[3];
+  const double a = pap > 0.0 ? rz / pap : 0.0;
+  double rz_new = rz - 2.0 * a * apdr + a * a * apdap;
+  if (rz_new < 0.0) rz_new = 0.0;
+  alpha = (T)a;
+  beta = rz > 0.0 ? (T)(rz_new / rz) : T(0);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(pap > 0.0)) sc->guard_hits += 1;
+}
+
+template <typename T, typename TL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cg(LevelView<T> L, CgIo<T> io) {
+  __shared__ T sp[3][TL::HALO];
+  __shared__ T sr[3][TL::HALO];
+  const TilePos<TL> t(L.nx, L.ny);
+  const size_t N = L.N;
+  const T* __restrict__ r_in = io.r_in;
+  const T* __restrict__ p_in = io.p_in;
+  const T* __restrict__ ap_in = io.ap_in;
+  const T* __restrict__ dinv = L.dinv;
+  // 1. halo inputs into registers
+  T hr[TL::HPT][3], hq[TL::HPT][3], hp[TL::HPT][3], ha[TL::HPT][3];
+  size_t hi[TL::HPT];
+  bool hin[TL::HPT];
+#pragma unroll
+  for (int h = 0; h < TL::HPT; ++h) {
+    const int k = threadIdx.x + h * kBlock;
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    hin[h] = k < TL::HALO && in_box(gx, gy, gz, L.nx, L.ny, L.nz);
+    hi[h] = hin[h] ? gx + (size_t)L.nx * (gy + (size_t)L.ny * gz) : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      hr[h][a] = T(0);
+      hq[h][a] = T(0);
+      hp[h][a] = T(0);
+      ha[h][a] = T(0);
+    }
+    if (hin[h]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t j = a * N + hi[h];
+        hr[h][a] = r_in[j];
+        hq[h][a] = dinv[j];
+        if (!FIRST) {
+          hp[h][a] = p_in[j];
+          ha[h][a] = ap_in[j];
+        }
+      }
+    }
+  }
+  // 2. CG scalars of the previous iterate
+  T alpha = T(0), beta = T(0);
+  if (!FIRST) cg_scalars<T>(io.s_in, io.n_in, alpha, beta, L.sc);
+  // 3. r_m, p_m into LDS; own nodes also store r_m, p_m and step d
+#pragma unroll
+  for (int h = 0; h < TL::HPT; ++h) {
+    const int k = threadIdx.x + h * kBlock;
+    if (k >= TL::HALO) continue;
+    T p3[3], r3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T r = hr[h][a];
+      if (!FIRST) r -= alpha * ha[h][a];
+      T p = hq[h][a] * r;
+      if (!FIRST) p += beta * hp[h][a];
+      r3[a] = r;
+      p3[a] = p;
+      sp[a][k] = p;
+      sr[a][k] = r;
+    }
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    if (hin[h] && lx >= 1 && lx <= TL::TX && ly >= 1 && ly <= TL::TY && lz >= 1 &&
+        lz <= TL::TZ) {
+      T* __restrict__ d = L.d;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t j = a * N + hi[h];
+        io.p_out[j] = p3[a];
+        if (!FIRST) {
+          io.r_out[j] = r3[a];
+          d[j] += alpha * hp[h][a];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // 4. A p_m on own nodes and the block partials of S_m
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    T o[3];
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o[0], o[1], o[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const size_t j = a * N + i;
+      io.ap_out[j] = o[a];
+      const double q = (double)dinv[j], r = (double)sr[a][c], p = (double)sp[a][c];
+      const double ap = (double)o[a];
+      part[0] += r * q * r;
+      part[1] += p * ap;
+      part[2] += ap * q * r;
+      part[3] += ap * q * ap;
+    }
+  }
+  write_block_partials<4>(part, io.s_out, gridDim.x);
+}
+
+// d += alpha p of the last CG iterate.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_final(LevelView<T> L, const T* __restrict__ p,
+                                                     const double* s, int n) {
+  T alpha, beta;
+  cg_scalars<T>(s, n, alpha, beta, L.sc);
   const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
   const size_t N = L.N;
   T* __restrict__ d = L.d;
-  T* __restrict__ r = L.r;
-  const T* __restrict__ ap = L.ap;
-  const T* __restrict__ dinv = L.dinv;
-  double part[1] = {0.0};
-  if (i < L.N) {
-    T pv[3], av[3], dv[3], rv[3], qv[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const size_t j = k * N + i;
-      pv[k] = p[j];
-      av[k] = ap[j];
-      dv[k] = d[j];
-      rv[k] = r[j];
-      qv[k] = dinv[j];
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const size_t j = k * N + i;
-      d[j] = dv[k] + alpha * pv[k];
-      const T rn = rv[k] - alpha * av[k];
-      r[j] = rn;
-      acc += (double)(rn * qv[k]) * (double)rn;
-    }
-    part[0] = acc;
-  }
-  write_block_partials<1>(part, red.out, 0);
+  for (int a = 0; a < 3; ++a) d[a * N + i] += alpha * p[a * N + i];
+}
+
+template <typename T, typename TL>
+void launch_cg_t(bool first, const LevelView<T>& L, const CgIo<T>& io, hipStream_t s) {
+  const int grid = tile_blocks(L.tile, L.nx, L.ny, L.nz);
+  if (first) k_cg<T, TL, true><<<grid, kBlock, 0, s>>>(L, io);
+  else k_cg<T, TL, false><<<grid, kBlock, 0, s>>>(L, io);
 }
 
 template <typename T>
-hipError_t launch_update(const LevelView<T>& L, const T* p_new, const Red& red, hipStream_t s) {
-  k_update<T><<<update_blocks(L.N), kBlock, 0, s>>>(L, p_new, red);
+hipError_t launch_cg(bool first, const LevelView<T>& L, const CgIo<T>& io, hipStream_t s) {
+  switch (L.tile) {
+    case 1: launch_cg_t<T, TileM>(first, L, io, s); break;
+    case 2: launch_cg_t<T, TileW>(first, L, io, s); break;
+    default: launch_cg_t<T, TileS>(first, L, io, s); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_final(const LevelView<T>& L, const T* p, const double* s_last, int n,
+                           hipStream_t st) {
+  k_cg_final<T><<<blocks_for(L.N), kBlock, 0, st>>>(L, p, s_last, n);
   return hipGetLastError();
 }
 
@@ -996,10 +1176,12 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_build_cells<T>(const LevelView<T>&, const RowView<T>&, T*, int,    \
                                             hipStream_t);                                       \
   template hipError_t launch_assemble_nodes<T>(const LevelView<T>&, const RowView<T>&,          \
-                                               hipStream_t);                                    \
-  template hipError_t launch_stencil<T>(int, const LevelView<T>&, const T*, T*, T*, T*,         \
-                                        const Red&, hipStream_t);                               \
-  template hipError_t launch_update<T>(const LevelView<T>&, const T*, const Red&, hipStream_t); \
+                                               const int*, const int*, int*, T*, hipStream_t);  \
+  template hipError_t launch_node_flags<T>(const LevelView<T>&, int*, hipStream_t);             \
+  template hipError_t launch_stencil<T>(int, const LevelView<T>&, const T*, T*, hipStream_t);   \
+  template hipError_t launch_cg<T>(bool, const LevelView<T>&, const CgIo<T>&, hipStream_t);     \
+  template hipError_t launch_cg_final<T>(const LevelView<T>&, const T*, const double*, int,     \
+                                         hipStream_t);                                          \
   template hipError_t launch_energy<T>(const LevelView<T>&, const RowView<T>&, int, double*,    \
                                        int, hipStream_t);                                       \
   template hipError_t launch_polar<T>(const LevelView<T>&, const T*, const T*, T*, hipStream_t); \

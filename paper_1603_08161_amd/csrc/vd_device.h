@@ -18,10 +18,24 @@ constexpr int kBlock = 256;   // threads per workgroup for every kernel
 constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kXcds = 8;      // MI355X: 8 accelerator dies, workgroups dealt round-robin
 
-// Tile of the stencil kernels: 8 x 8 x 4 nodes, one node per thread.
-constexpr int kTX = 8, kTY = 8, kTZ = 4;
-constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
-constexpr int kHalo = kHX * kHY * kHZ;  // 600
+// Tiles of the stencil kernels: TX x TY x TZ nodes staged in LDS with a
+// one-node halo; 256 threads, each owning NPT consecutive nodes along z.
+template <int TX_, int TY_, int TZ_>
+struct Tile {
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
+  static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  static constexpr int HALO = HX * HY * HZ;
+  static constexpr int ZG = 256 / (TX * TY);     // thread layers along z
+  static constexpr int NPT = TZ / ZG;            // nodes per thread
+  static constexpr int HPT = (HALO + 255) / 256;  // halo nodes staged per thread
+};
+// Tile kinds: small (most workgroups, best latency hiding), medium (half the
+// block partials and 1.95x instead of 2.34x halo reads), wide (128-byte rows
+// along x, 4x fewer block partials, one workgroup per CU on 64^3).
+using TileS = Tile<8, 8, 4>;
+using TileM = Tile<8, 8, 8>;
+using TileW = Tile<32, 8, 4>;
+constexpr int kTileKinds = 3;
 
 // Maps the hardware workgroup id to a logical tile id so that each XCD gets a
 // contiguous range of tiles (neighbouring tiles then share that XCD's L2).
@@ -87,6 +101,39 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
   return total;
 }
 
+// Sums of K partial arrays p + k*n (k < K) in one pass (one round of loads),
+// identical in every block; result valid in every thread.
+template <int K>
+__device__ __forceinline__ void sum_partials_k(const double* __restrict__ p, int n,
+                                               double (&out)[K]) {
+  __shared__ double lds[K * (kBlock / kWave)];
+  __shared__ double total[K];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < n; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += p[(size_t)k * n + b];
+  }
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k * (kBlock / kWave) + wid] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) s += lds[threadIdx.x * (kBlock / kWave) + w];
+    total[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = total[k];
+}
+
 // Block-wide sums of K values written to out[k * stride + blockIdx.x].
 template <int K>
 __device__ __forceinline__ void write_block_partials(double (&v)[K], double* out, int stride) {
@@ -133,8 +180,12 @@ struct Fit {
   T gap;             // lambda_1 - lambda_2 of Horn's matrix = 2 (sigma2 + d sigma3)
 };
 
+// The rotation-fit routines are __host__ __device__ so their logic can also
+// be exercised on the CPU.
+#define VD_HD __host__ __device__ __forceinline__
+
 template <typename T>
-__device__ __forceinline__ void jacobi_rotate(T (&A)[4][4], T (&V)[4][4], int p, int q) {
+VD_HD void jacobi_rotate(T (&A)[4][4], T (&V)[4][4], int p, int q) {
   const T apq = A[p][q];
   if (apq == T(0)) return;
   const T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
@@ -162,20 +213,73 @@ __device__ __forceinline__ void jacobi_rotate(T (&A)[4][4], T (&V)[4][4], int p,
   }
 }
 
+// Unit quaternion (w, x, y, z) of a rotation matrix (Shepperd's method:
+// branch on the largest of the trace and the diagonal).  Falls back to the
+// identity when R is too far from a rotation to give a finite unit vector.
+template <typename T>
+VD_HD void rot_to_quat(const T (&R)[9], T (&q)[4]) {
+  const T tr = R[0] + R[4] + R[8];
+  T w, x, y, z;
+  if (tr > R[0] && tr > R[4] && tr > R[8]) {
+    const T s = T(2) * sqrt(fmax(tr + T(1), T(0)));
+    w = T(0.25) * s; x = (R[7] - R[5]) / s; y = (R[2] - R[6]) / s; z = (R[3] - R[1]) / s;
+  } else if (R[0] > R[4] && R[0] > R[8]) {
+    const T s = T(2) * sqrt(fmax(T(1) + R[0] - R[4] - R[8], T(0)));
+    w = (R[7] - R[5]) / s; x = T(0.25) * s; y = (R[1] + R[3]) / s; z = (R[2] + R[6]) / s;
+  } else if (R[4] > R[8]) {
+    const T s = T(2) * sqrt(fmax(T(1) + R[4] - R[0] - R[8], T(0)));
+    w = (R[2] - R[6]) / s; x = (R[1] + R[3]) / s; y = T(0.25) * s; z = (R[5] + R[7]) / s;
+  } else {
+    const T s = T(2) * sqrt(fmax(T(1) + R[8] - R[0] - R[4], T(0)));
+    w = (R[3] - R[1]) / s; x = (R[2] + R[6]) / s; y = (R[5] + R[7]) / s; z = T(0.25) * s;
+  }
+  const T n2 = w * w + x * x + y * y + z * z;
+  if (!(n2 > T(1e-6) && n2 < T(1e30))) {  // also rejects NaN and inf
+    q[0] = T(1); q[1] = T(0); q[2] = T(0); q[3] = T(0);
+    return;
+  }
+  const T inv = T(1) / sqrt(n2);
+  q[0] = w * inv; q[1] = x * inv; q[2] = y * inv; q[3] = z * inv;
+}
+
 // Horn (1987): with S = M^T (sum source * target^T), the rotation is given by
 // the unit quaternion spanning the top eigenvector of the symmetric N below.
+// N is first expressed in the basis L(q0) (quaternion left-multiplication by
+// the previous rotation's quaternion), where it is nearly diagonal with its
+// top eigenvector near e0, so the cyclic Jacobi sweeps converge in one or
+// two passes; they stop once the off-diagonal mass is negligible.
 template <typename T, int SWEEPS>
-__device__ __forceinline__ void fit_rotation(const T (&M)[9], Fit<T>& out) {
+VD_HD void fit_rotation(const T (&M)[9], const T (&q0)[4], Fit<T>& out) {
   const T Sxx = M[0], Sxy = M[3], Sxz = M[6];
   const T Syx = M[1], Syy = M[4], Syz = M[7];
   const T Szx = M[2], Szy = M[5], Szz = M[8];
-  T A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
-               {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
-               {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
-               {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+  const T Nm[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                      {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                      {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                      {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+  const T w = q0[0], x = q0[1], y = q0[2], z = q0[3];
+  const T Lq[4][4] = {{w, -x, -y, -z}, {x, w, -z, y}, {y, z, w, -x}, {z, -y, x, w}};
+  T NL[4][4], A[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      NL[r][c] = Nm[r][0] * Lq[0][c] + Nm[r][1] * Lq[1][c] + Nm[r][2] * Lq[2][c] +
+                 Nm[r][3] * Lq[3][c];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      A[r][c] = Lq[0][r] * NL[0][c] + Lq[1][r] * NL[1][c] + Lq[2][r] * NL[2][c] +
+                Lq[3][r] * NL[3][c];
   T V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+  const T tol = sizeof(T) == 4 ? T(1e-14) : T(1e-30);
 #pragma unroll 1
   for (int sweep = 0; sweep < SWEEPS; ++sweep) {
+    const T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[0][3] * A[0][3] +
+                  A[1][2] * A[1][2] + A[1][3] * A[1][3] + A[2][3] * A[2][3];
+    const T dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2] + A[3][3] * A[3][3];
+    if (off <= tol * dia) break;
     jacobi_rotate(A, V, 0, 1);
     jacobi_rotate(A, V, 0, 2);
     jacobi_rotate(A, V, 0, 3);
@@ -183,16 +287,27 @@ __device__ __forceinline__ void fit_rotation(const T (&M)[9], Fit<T>& out) {
     jacobi_rotate(A, V, 1, 3);
     jacobi_rotate(A, V, 2, 3);
   }
+  // back to the original basis: eigenvectors of N are L(q0) V
+  T W[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      W[r][c] = Lq[r][0] * V[0][c] + Lq[r][1] * V[1][c] + Lq[r][2] * V[2][c] + Lq[r][3] * V[3][c];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) V[r][c] = W[r][c];
   // sort the four eigenvalues (descending) while tracking the top vector
   T l[4] = {A[0][0], A[1][1], A[2][2], A[3][3]};
   int top = 0;
 #pragma unroll
   for (int k = 1; k < 4; ++k)
     if (l[k] > l[top]) top = k;
-  T q0 = V[0][0], q1 = V[1][0], q2 = V[2][0], q3 = V[3][0];
+  T e0 = V[0][0], e1 = V[1][0], e2 = V[2][0], e3 = V[3][0];
 #pragma unroll
   for (int k = 1; k < 4; ++k)
-    if (k == top) { q0 = V[0][k]; q1 = V[1][k]; q2 = V[2][k]; q3 = V[3][k]; }
+    if (k == top) { e0 = V[0][k]; e1 = V[1][k]; e2 = V[2][k]; e3 = V[3][k]; }
   // descending order of the eigenvalues (4-element sorting network)
   T s0 = l[0], s1 = l[1], s2 = l[2], s3 = l[3], tmp;
 #define VD_CSWAP(a, b) if (a < b) { tmp = a; a = b; b = tmp; }
@@ -201,17 +316,17 @@ __device__ __forceinline__ void fit_rotation(const T (&M)[9], Fit<T>& out) {
   out.sigma1 = T(0.5) * (s0 + s1);
   out.sigma2 = T(0.5) * (s0 + s2);
   out.gap = s0 - s1;
-  const T nq = T(1) / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const T w = q0 * nq, x = q1 * nq, y = q2 * nq, z = q3 * nq;
-  out.R[0] = w * w + x * x - y * y - z * z;
-  out.R[1] = T(2) * (x * y - w * z);
-  out.R[2] = T(2) * (x * z + w * y);
-  out.R[3] = T(2) * (x * y + w * z);
-  out.R[4] = w * w - x * x + y * y - z * z;
-  out.R[5] = T(2) * (y * z - w * x);
-  out.R[6] = T(2) * (x * z - w * y);
-  out.R[7] = T(2) * (y * z + w * x);
-  out.R[8] = w * w - x * x - y * y + z * z;
+  const T nq = T(1) / sqrt(e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3);
+  const T qw = e0 * nq, qx = e1 * nq, qy = e2 * nq, qz = e3 * nq;
+  out.R[0] = qw * qw + qx * qx - qy * qy - qz * qz;
+  out.R[1] = T(2) * (qx * qy - qw * qz);
+  out.R[2] = T(2) * (qx * qz + qw * qy);
+  out.R[3] = T(2) * (qx * qy + qw * qz);
+  out.R[4] = qw * qw - qx * qx + qy * qy - qz * qz;
+  out.R[5] = T(2) * (qy * qz - qw * qx);
+  out.R[6] = T(2) * (qx * qz - qw * qy);
+  out.R[7] = T(2) * (qy * qz + qw * qx);
+  out.R[8] = qw * qw - qx * qx - qy * qy + qz * qz;
 }
 
 // Rank(M) <= 1 (sigma2 <= 1e-12 sigma1): the fit is not unique.
@@ -226,13 +341,15 @@ enum FitCode { kFitOk = 0, kFitFp64 = 1, kFitKeep = 2 };
 // Fit R from M; precision T, with the float64 refit / keep rules.  R_prev is
 // kept when the fit is degenerate.
 template <typename T>
-__device__ __forceinline__ int fit_or_keep(const T (&M)[9], const T (&R_prev)[9], T (&R)[9]);
+VD_HD int fit_or_keep(const T (&M)[9], const T (&R_prev)[9], T (&R)[9]);
 
 template <>
-__device__ __forceinline__ int fit_or_keep<double>(const double (&M)[9], const double (&R_prev)[9],
+VD_HD int fit_or_keep<double>(const double (&M)[9], const double (&R_prev)[9],
                                                    double (&R)[9]) {
   Fit<double> f;
-  fit_rotation<double, 10>(M, f);
+  double q0[4];
+  rot_to_quat<double>(R_prev, q0);
+  fit_rotation<double, 10>(M, q0, f);
   if (!(f.sigma2 > kDegenerateRatio * f.sigma1)) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = R_prev[k];
@@ -244,10 +361,12 @@ __device__ __forceinline__ int fit_or_keep<double>(const double (&M)[9], const d
 }
 
 template <>
-__device__ __forceinline__ int fit_or_keep<float>(const float (&M)[9], const float (&R_prev)[9],
+VD_HD int fit_or_keep<float>(const float (&M)[9], const float (&R_prev)[9],
                                                   float (&R)[9]) {
   Fit<float> f;
-  fit_rotation<float, 6>(M, f);
+  float q0[4];
+  rot_to_quat<float>(R_prev, q0);
+  fit_rotation<float, 6>(M, q0, f);
   if (f.gap > kRefitRatio * f.sigma1 && f.sigma1 > 0.0f) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = f.R[k];

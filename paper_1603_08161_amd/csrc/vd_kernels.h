@@ -33,6 +33,7 @@ template <typename T>
 struct LevelView {
   int nx, ny, nz;
   int N;            // nx * ny * nz
+  int tile;         // tile kind of the stencil / CG kernels
   T h;              // node spacing of this level
   T wr;             // w_arap
   // node vectors, SoA [3][N] (rot: [9][N], row-major entries)
@@ -46,19 +47,10 @@ struct LevelView {
   // constraint cache
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
+  const int* node_slot; // node -> slot in A27, -1 if no data term touches it
+  const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
+  int capA;             // slots allocated in A27
   Scalars* sc;
-};
-
-// Reduction plumbing of one launch: partials of the scalars it consumes
-// (written by earlier kernels) and the array its own block partials go to.
-struct Red {
-  const double* cur;   // r^T D^-1 r partials of the current CG iterate
-  int n_cur;
-  const double* prev;  // ... of the previous iterate (null on the first iteration)
-  int n_prev;
-  const double* pap;   // p^T A p partials (phase B)
-  int n_pap;
-  double* out;         // this launch's block partials
 };
 
 // Constraint rows of one level (dense rows then 3 rows per sparse pair).
@@ -106,22 +98,46 @@ hipError_t launch_build_cells(const LevelView<T>& L, const RowView<T>& R, T* K, 
                               hipStream_t s);
 
 template <typename T>
-hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, hipStream_t s);
+hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s);
+
+template <typename T>
+hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
+                                 const int* scan, int* node_slot, T* A27, hipStream_t s);
 
 // ---- solve ---------------------------------------------------------------
-enum StencilMode { kModePcg = 0, kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
+enum StencilMode { kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
 
-// Number of workgroups (= block partials) of the stencil and update kernels.
-int stencil_blocks(int nx, int ny, int nz);
+// Workgroups (= block partials) of the stencil and CG kernels for a tile kind
+// (0: 8x8x4, 1: 8x8x8, 2: 32x8x4), and the kind used when none is chosen.
+int tile_blocks(int kind, int nx, int ny, int nz);
+int default_tile(int nx, int ny, int nz);
 int update_blocks(int N);
 int energy_blocks(int cap_rows, int N);
 
+// Gradient pass (r = -J^T r into L.r) or the test entry points A p / J^T r.
 template <typename T>
-hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, T* p_old,
-                          T* p_new, const Red& red, hipStream_t s);
+hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, hipStream_t s);
+
+// Buffers of one fused CG iteration (see k_cg).
+template <typename T>
+struct CgIo {
+  const T* r_in;
+  T* r_out;
+  const T* p_in;
+  T* p_out;
+  const T* ap_in;
+  T* ap_out;
+  const double* s_in;
+  int n_in;
+  double* s_out;
+};
 
 template <typename T>
-hipError_t launch_update(const LevelView<T>& L, const T* p_new, const Red& red, hipStream_t s);
+hipError_t launch_cg(bool first, const LevelView<T>& L, const CgIo<T>& io, hipStream_t s);
+
+template <typename T>
+hipError_t launch_cg_final(const LevelView<T>& L, const T* p, const double* s_last, int n,
+                           hipStream_t s);
 
 // Energy over the rows (count read from sc->rows; grid sized by `cap_rows`)
 // and the ARAP edges of level L; block partials go to part[3][energy_blocks],

@@ -37,10 +37,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "vd.h"
 int main(void) {
-  printf("desc %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vd_lattice_desc),
+  printf("desc %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vd_lattice_desc),
          offsetof(vd_lattice_desc, spacing), offsetof(vd_lattice_desc, num_levels),
          offsetof(vd_lattice_desc, pcg_iters), offsetof(vd_lattice_desc, w_dense),
-         offsetof(vd_lattice_desc, precision), offsetof(vd_lattice_desc, flags));
+         offsetof(vd_lattice_desc, precision), offsetof(vd_lattice_desc, flags),
+         offsetof(vd_lattice_desc, tile));
   printf("cons %zu %zu %zu\n", sizeof(vd_constraints), offsetof(vd_constraints, n_sparse),
          offsetof(vd_constraints, mem));
   printf("rep %zu %zu %zu %zu\n", sizeof(vd_solve_report), offsetof(vd_solve_report, n_trace),
@@ -58,7 +59,7 @@ int main(void) {
     D = L.LatticeDesc
     assert out["desc"] == [ctypes.sizeof(D), D.spacing.offset, D.num_levels.offset,
                            D.pcg_iters.offset, D.w_dense.offset, D.precision.offset,
-                           D.flags.offset]
+                           D.flags.offset, D.tile.offset]
     Cs = L.Constraints
     assert out["cons"] == [ctypes.sizeof(Cs), Cs.n_sparse.offset, Cs.mem.offset]
     R = L.SolveReport
@@ -80,6 +81,7 @@ def test_create_rejects_bad_descriptors_without_a_gpu():
         dict(good, num_levels=5),
         dict(good, dims=(3, 3, 3), num_levels=3),  # 3 -> 2 -> 1
         dict(good, origin=(0, float("inf"), 0)),
+        dict(good, tile=4),
     ]
     for c in cases:
         d = LatticeDesc()
@@ -88,6 +90,7 @@ def test_create_rejects_bad_descriptors_without_a_gpu():
             d.origin[k] = c["origin"][k]
         d.spacing = c["spacing"]
         d.num_levels = c["num_levels"]
+        d.tile[1] = c.get("tile", 0)
         d.w_dense, d.w_sparse, d.w_arap = 1.0, 10.0, 5.0
         h = ctypes.c_void_p()
         assert lib.vd_lattice_create(ctypes.byref(d), None, ctypes.byref(h)) == vd.VD_EINVAL, c
