@@ -87,6 +87,7 @@ extern "C" {
 #define VD_MAX_TRACE 512
 
 typedef struct vd_lattice vd_lattice;
+typedef struct vd_batch vd_batch;
 
 /* Lattice description.  dims[] are the finest level's node counts (>= 2);
  * level l-1 has ceil(n_l / 2) nodes per axis and twice the spacing, all levels
@@ -177,6 +178,24 @@ int vd_set_constraints(vd_lattice* l, const vd_constraints* c);
  * finest result becomes the state.  Asynchronous unless `report` is non-NULL.
  * VD_ESTATE if no constraints were set. */
 int vd_solve_frame(vd_lattice* l, const vd_solve_opts* opts, vd_solve_report* report);
+
+/* Batched solve of several independent lattices (same precision, number of
+ * levels, schedule and stream; any sizes).  Every step of the frame schedule
+ * is one launch covering the workgroups of all lattices, with per-lattice
+ * reductions.  The batch does not own the handles: they must outlive it.
+ * Creating it sets every handle's stencil tile, per level, to the tile of
+ * the largest lattice at that level.  VD_EINVAL on mismatched handles. */
+int vd_batch_create(vd_lattice* const* lattices, int32_t n, vd_batch** out);
+
+/* Solve one frame of every lattice of the batch (Sec. 7, as vd_solve_frame);
+ * VD_ESTATE if a handle has no constraints.  energies (may be NULL) receives
+ * n x 4 values, eq. (1) per lattice, after waiting for the stream; without it
+ * the call is asynchronous.  The schedule is replayed from a hipGraph when
+ * the first handle was created with VD_FLAG_GRAPH. */
+int vd_batch_solve(vd_batch* b, const vd_solve_opts* opts, double* energies);
+
+/* Free the batch (not the handles).  NULL is a no-op. */
+int vd_batch_destroy(vd_batch* b);
 
 /* Energy terms at the current finest state, eq. (1): out = {E_total,
  * w_d E_dense, w_s E_sparse, w_r E_reg}.  Waits for the stream. */

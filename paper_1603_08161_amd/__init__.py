@@ -8,6 +8,7 @@ loudly if it has not been built.
 from ._lib import (  # noqa: F401
     EXPORTED,
     LIB_PATH,
+    Batch,
     Lattice,
     VDError,
     fit_rotations,

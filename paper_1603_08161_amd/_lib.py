@@ -40,6 +40,7 @@ EXPORTED = (
     "vd_get_energy", "vd_get_state", "vd_set_state", "vd_level_info", "vd_strerror",
     "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
     "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong", "vd_tune",
+    "vd_batch_create", "vd_batch_solve", "vd_batch_destroy",
 )
 
 
@@ -122,6 +123,9 @@ def _load() -> C.CDLL:
         "vd_debug_fit_rotations": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
         "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
         "vd_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
+        "vd_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
+        "vd_batch_solve": ([vp, C.POINTER(SolveOpts), dp], C.c_int),
+        "vd_batch_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -355,6 +359,39 @@ class Lattice:
         _check(_lib.vd_debug_prolong(self._h, level, coarse.ctypes.data, out.ctypes.data,
                                      VD_MEM_HOST), "vd_debug_prolong")
         return out
+
+
+class Batch:
+    """A batch of lattice handles solved together (vd_batch*): one launch per
+    schedule step covers every lattice.  Keeps references to the handles."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        arr = (C.c_void_p * len(self.lattices))(*[l._h.value for l in self.lattices])
+        h = C.c_void_p()
+        _check(_lib.vd_batch_create(arr, len(self.lattices), C.byref(h)), "vd_batch_create")
+        self._h = h
+
+    def solve(self, reset: bool = False, energies: bool = False):
+        o = SolveOpts()
+        o.reset_to_rest = 1 if reset else 0
+        if not energies:
+            _check(_lib.vd_batch_solve(self._h, C.byref(o), None), "vd_batch_solve")
+            return None
+        out = (C.c_double * (4 * len(self.lattices)))()
+        _check(_lib.vd_batch_solve(self._h, C.byref(o), out), "vd_batch_solve")
+        return np.array(out[:]).reshape(-1, 4)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.vd_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fit_rotations(M, R_prev=None, precision: str = "fp32", stream: Optional[int] = None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vd.h"
@@ -66,15 +67,13 @@ template <typename T>
 struct LevelData {
   int nx = 0, ny = 0, nz = 0, N = 0, ncell = 0;
   double h = 0;
-  T *d = nullptr, *r = nullptr, *pa = nullptr, *pb = nullptr, *ap = nullptr, *dinv = nullptr,
-    *bnode = nullptr, *base = nullptr, *rot = nullptr;
+  T *d = nullptr, *r = nullptr, *r2 = nullptr, *pa = nullptr, *pb = nullptr, *ap = nullptr,
+    *ap2 = nullptr, *dinv = nullptr, *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
   int* node_slot = nullptr;  // node -> row of A27 (-1: no data term)
   T* A27 = nullptr;          // [27*6][N] data blocks of A, per node slot
   Scalars* sc = nullptr;
-  T* r2 = nullptr;                      // second CG residual buffer (ping-pong with r)
-  T* ap2 = nullptr;                     // second A p buffer (ping-pong with ap)
-  double* scg[2] = {nullptr, nullptr};  // CG block partials [4][ntiles], alternating
+  double* scg[2] = {nullptr, nullptr};  // CG block partials [4][max_tiles], alternating
   double* pe = nullptr;                 // energy block partials [3][energy blocks]
   int cap_pe = 0;                       // doubles in pe
   // constraint rows and cell cache
@@ -85,13 +84,19 @@ struct LevelData {
   int max_tiles = 0;  // most workgroups over all tile kinds (partials capacity)
   int tile = 0;       // tile kind of the stencil / CG kernels
 
+  int rblocks() const { return blocks_of(cap_rows); }
+
   LevelView<T> view(double wr) const {
-    LevelView<T> v;
-    v.nx = nx; v.ny = ny; v.nz = nz; v.N = N; v.tile = tile;
+    LevelView<T> v{};
+    v.nx = nx; v.ny = ny; v.nz = nz; v.N = N; v.tile = tile; v.ntiles = ntiles;
+    v.rblocks = rblocks();
     v.h = (T)h; v.wr = (T)wr;
-    v.d = d; v.r = r; v.ap = ap; v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
-    v.cell_map = cell_map; v.K = K; v.sc = sc;
-    v.node_slot = node_slot; v.A27 = A27; v.capA = N;
+    v.d = d; v.r = r; v.r2 = r2; v.pa = pa; v.pb = pb; v.ap = ap; v.ap2 = ap2;
+    v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
+    v.scg0 = scg[0]; v.scg1 = scg[1]; v.pe = pe;
+    v.cell_map = cell_map; v.K = K; v.node_slot = node_slot; v.A27 = A27; v.capA = N;
+    v.row_cell = row_cell; v.row_f = row_f; v.row_sn = row_sn; v.row_rho = row_rho;
+    v.sc = sc;
     return v;
   }
   RowView<T> rows_view(int rows, int n_dense) const {
@@ -102,6 +107,16 @@ struct LevelData {
     return v;
   }
 };
+
+// Single-lattice dispatches of the four workgroup kinds.
+template <typename T>
+Dispatch<T> tiles_of(const LevelView<T>& V) { return single(V, V.ntiles); }
+template <typename T>
+Dispatch<T> nodes_of(const LevelView<T>& V) { return single(V, node_blocks(V.N)); }
+template <typename T>
+Dispatch<T> energy_of(const LevelView<T>& V) { return single(V, energy_blocks(V.rblocks, V.N)); }
+template <typename T>
+Dispatch<T> one_of(const LevelView<T>& V) { return single(V, 1); }
 
 int bits_for(int n) {
   int b = 1;
@@ -196,7 +211,7 @@ class Solver final : public ISolver {
     VD_CHECK(pool_.alloc(&d_flags_, 4));
     VD_TRY(hipHostMalloc((void**)&h_flags_, 4 * sizeof(int), hipHostMallocDefault));
     VD_TRY(hipHostMalloc((void**)&h_sc_, sizeof(Scalars), hipHostMallocDefault));
-    VD_TRY(launch_set_rest<T>(finest().view(desc_.w_arap), stream_));
+    VD_TRY(launch_set_rest<T>(nodes_of(finest().view(desc_.w_arap)), stream_));
     VD_TRY(hipStreamSynchronize(stream_));
     return VD_OK;
   }
@@ -256,7 +271,7 @@ class Solver final : public ISolver {
       VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, node_flags_, node_scan_, v.N, stream_));
       VD_TRY(launch_assemble_nodes<T>(V, R, node_flags_, node_scan_, v.node_slot, v.A27,
                                       stream_));
-      VD_TRY(launch_reset_counters(v.sc, rows, C, 1, stream_));
+      VD_TRY(launch_set_counts(v.sc, rows, C, stream_));
     }
     rows_ = rows;
     n_dense_ = C;
@@ -308,8 +323,8 @@ class Solver final : public ISolver {
     if (!have_constraints_) return VD_ESTATE;
     LevelData<T>& F = finest();
     if (!energy_fresh_) {
-      VD_TRY(launch_energy<T>(F.view(desc_.w_arap), F.rows_view(rows_, n_dense_), F.cap_rows,
-                              F.pe, 0, stream_));
+      const LevelView<T> V = F.view(desc_.w_arap);
+      VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, stream_));
       energy_fresh_ = true;
     }
     VD_TRY(hipMemcpyAsync(h_sc_, F.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
@@ -368,6 +383,30 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
+  // ---- accessors used by the batched solve ---------------------------
+  int levels() const { return L_; }
+  LevelView<T> level_view(int l) const { return lv_[l].view(desc_.w_arap); }
+  long generation() const { return alloc_gen_; }
+  hipStream_t stream() const { return stream_; }
+  bool has_constraints() const { return have_constraints_; }
+  void mark_energy_fresh() { energy_fresh_ = true; }
+  const vd_lattice_desc& desc() const { return desc_; }
+  int level_nodes(int l) const { return lv_[l].N; }
+  int level_tile(int l) const { return lv_[l].tile; }
+  void force_tile(int l, int kind) {
+    if (lv_[l].tile == kind) return;
+    lv_[l].tile = kind;
+    lv_[l].ntiles = tile_blocks(kind, lv_[l].nx, lv_[l].ny, lv_[l].nz);
+    desc_.tile[l] = kind + 1;
+    ++alloc_gen_;
+  }
+  int finest_energy_host(double out[4]) {
+    if (hipMemcpy(h_sc_, finest().sc, sizeof(Scalars), hipMemcpyDeviceToHost) != hipSuccess)
+      return VD_EHIP;
+    for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
+    return VD_OK;
+  }
+
   int level_info(int level, int dims[3], double* h) const override {
     if (level < 0 || level >= L_) return VD_EINVAL;
     const LevelData<T>& v = lv_[level];
@@ -385,7 +424,8 @@ class Solver final : public ISolver {
     const int N = v.N;
     VD_CHECK(upload_aos(p, 3 * N, mem));
     VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, N, stream_));
-    VD_TRY(launch_stencil<T>(kModeApply, v.view(desc_.w_arap), dbg_t1_, dbg_t2_, stream_));
+    VD_TRY(launch_stencil<T>(kModeApply, tiles_of(v.view(desc_.w_arap)), dbg_t1_, dbg_t2_,
+                             stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(ap, 3 * N, mem);
   }
@@ -396,7 +436,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot, mem, &V));
     const int N = V.N;
-    VD_TRY(launch_stencil<T>(kModeGrad, V, V.d, dbg_t2_, stream_));
+    VD_TRY(launch_stencil<T>(kModeGrad, tiles_of(V), V.d, dbg_t2_, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, N, stream_));
     return download_aos(g, 3 * N, mem);
   }
@@ -407,7 +447,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot, mem, &V));
     LevelData<T>& v = lv_[level];
-    VD_TRY(launch_energy<T>(V, v.rows_view(rows_, n_dense_), v.cap_rows, v.pe, 0, stream_));
+    VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, stream_));
     VD_TRY(hipMemcpyAsync(h_sc_, v.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
     VD_TRY(hipStreamSynchronize(stream_));
     for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
@@ -444,7 +484,7 @@ class Solver final : public ISolver {
     LevelView<T> V;
     VD_CHECK(scratch_view(level, pos, rot_prev, mem, &V));
     const size_t N = V.N;
-    VD_TRY(launch_polar<T>(V, V.d, V.rot, V.rot, stream_));
+    VD_TRY(launch_polar<T>(nodes_of(V), stream_));
     float* drot = dbg_f_ + 3 * N;
     VD_TRY(launch_state_io<T>(V, desc_.origin, nullptr, drot, nullptr, nullptr, 0, d_flags_,
                               stream_));
@@ -464,8 +504,11 @@ class Solver final : public ISolver {
     LevelData<T>& f = lv_[level];
     VD_CHECK(upload_aos(coarse, 3 * c.N, mem));
     VD_TRY(launch_convert<T>(dbg_f_, dbg_t1_, c.N, stream_));
-    VD_TRY(launch_prolong_add<T>(c.view(desc_.w_arap), f.view(desc_.w_arap), dbg_t1_, nullptr,
-                                 dbg_t2_, 0, stream_));
+    LevelView<T> Cv = c.view(desc_.w_arap), Fv = f.view(desc_.w_arap);
+    Cv.d = dbg_t1_;
+    Cv.base = nullptr;
+    Fv.d = dbg_t2_;
+    VD_TRY(launch_prolong<T>(nodes_of(Fv), nodes_of(Cv), 0, stream_));
     VD_TRY(launch_convert_back<T>(dbg_t2_, dbg_f_, f.N, stream_));
     return download_aos(out, 3 * f.N, mem);
   }
@@ -492,28 +535,12 @@ class Solver final : public ISolver {
         v.tile = kind;
         v.ntiles = tile_blocks(kind, v.nx, v.ny, v.nz);
         const LevelView<T> V = v.view(wr);
-        T* rb[2] = {v.r, v.r2};
-        T* pb[2] = {v.pa, v.pb};
-        T* ab[2] = {v.ap, v.ap2};
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {  // first pass warms up
           VD_TRY(hipMemcpyAsync(v.d, saved, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
-          VD_TRY(launch_stencil<T>(kModeRhs, V, nullptr, nullptr, stream_));
+          VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, stream_));
           VD_TRY(hipEventRecord(e0, stream_));
-          for (int m = 0; m < iters; ++m) {
-            CgIo<T> io{};
-            const int cur = m % 2, prv = (m + 1) % 2;
-            io.r_in = m == 0 ? rb[0] : rb[prv];
-            io.r_out = rb[cur];
-            io.p_in = pb[prv];
-            io.p_out = pb[cur];
-            io.ap_in = ab[prv];
-            io.ap_out = ab[cur];
-            io.s_in = v.scg[prv];
-            io.n_in = v.ntiles;
-            io.s_out = v.scg[cur];
-            VD_TRY(launch_cg<T>(m == 0, V, io, stream_));
-          }
+          for (int m = 0; m < iters; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), stream_));
           VD_TRY(hipEventRecord(e1, stream_));
           VD_TRY(hipEventSynchronize(e1));
           VD_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -551,62 +578,37 @@ class Solver final : public ISolver {
     const bool prof = (desc_.flags & VD_FLAG_PROFILE) && !(desc_.flags & VD_FLAG_GRAPH);
     prof_.clear();
     ev_used_ = 0;
-    LevelData<T>& F = finest();
-    if (reset) VD_TRY(launch_set_rest<T>(F.view(wr), s));
-    for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters(lv_[l].sc, -1, -1, 1, s));
+    const LevelView<T> FV = finest().view(wr);
+    if (reset) VD_TRY(launch_set_rest<T>(nodes_of(FV), s));
+    for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters<T>(one_of(lv_[l].view(wr)), s));
     for (int l = 0; l < L_; ++l) {
       LevelData<T>& v = lv_[l];
       const LevelView<T> V = v.view(wr);
-      const RowView<T> R = v.rows_view(rows_, n_dense_);
       const bool on = prof && l == L_ - 1;
-      if (l < L_ - 1) VD_TRY(launch_inject<T>(F.view(wr), V, 1 << (L_ - 1 - l), s));
+      if (l < L_ - 1) VD_TRY(launch_inject<T>(nodes_of(V), nodes_of(FV), 1 << (L_ - 1 - l), s));
       if (l > 0) {
-        LevelData<T>& c = lv_[l - 1];
-        VD_CHECK(timed(on, VD_PROF_TRANSFER, s, [&] {
-          return launch_prolong_add<T>(c.view(wr), V, c.d, c.base, v.d, 1, s);
-        }));
-        VD_CHECK(timed(on, VD_PROF_ROTATION, s,
-                       [&] { return launch_polar<T>(V, v.d, v.rot, v.rot, s); }));
+        const LevelView<T> C = lv_[l - 1].view(wr);
+        VD_CHECK(timed(on, VD_PROF_TRANSFER, s,
+                       [&] { return launch_prolong<T>(nodes_of(V), nodes_of(C), 1, s); }));
+        VD_CHECK(timed(on, VD_PROF_ROTATION, s, [&] { return launch_polar<T>(nodes_of(V), s); }));
       }
       const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
-      // CG iterate m keeps r_m, p_m, Ap_m and its block partials S_m in
-      // buffer m % 2 of each pair (k_cg reads iterate m-1 from the other).
-      T* rb[2] = {v.r, v.r2};
-      T* pb[2] = {v.pa, v.pb};
-      T* ab[2] = {v.ap, v.ap2};
       for (int k = 0; k < gn; ++k) {
         VD_CHECK(timed(on, VD_PROF_GRADIENT, s, [&] {
-          return launch_stencil<T>(kModeRhs, V, nullptr, nullptr, s);
+          return launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s);
         }));
-        for (int m = 0; m < pcg; ++m) {
-          CgIo<T> io{};
-          const int cur = m % 2, prv = (m + 1) % 2;
-          io.r_in = m == 0 ? rb[0] : rb[prv];
-          io.r_out = rb[cur];
-          io.p_in = pb[prv];
-          io.p_out = pb[cur];
-          io.ap_in = ab[prv];
-          io.ap_out = ab[cur];
-          io.s_in = v.scg[prv];
-          io.n_in = v.ntiles;
-          io.s_out = v.scg[cur];
-          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] { return launch_cg<T>(m == 0, V, io, s); }));
-        }
-        if (pcg > 0) {
-          const int last = (pcg - 1) % 2;
-          VD_CHECK(timed(on, VD_PROF_CG_B, s, [&] {
-            return launch_cg_final<T>(V, pb[last], v.scg[last], v.ntiles, s);
-          }));
-        }
-        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, v.pe, 1, s));
-        VD_CHECK(timed(on, VD_PROF_ROTATION, s,
-                       [&] { return launch_polar<T>(V, v.d, v.rot, v.rot, s); }));
-        if (trace) VD_TRY(launch_energy<T>(V, R, v.cap_rows, v.pe, 1, s));
+        for (int m = 0; m < pcg; ++m)
+          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] { return launch_cg<T>(m, tiles_of(V), s); }));
+        if (pcg > 0)
+          VD_CHECK(timed(on, VD_PROF_CG_B, s,
+                         [&] { return launch_cg_final<T>(pcg - 1, nodes_of(V), s); }));
+        if (trace) VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 1, s));
+        VD_CHECK(timed(on, VD_PROF_ROTATION, s, [&] { return launch_polar<T>(nodes_of(V), s); }));
+        if (trace) VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 1, s));
       }
     }
-    VD_CHECK(timed(prof, VD_PROF_ENERGY, s, [&] {
-      return launch_energy<T>(F.view(wr), F.rows_view(rows_, n_dense_), F.cap_rows, F.pe, 0, s);
-    }));
+    VD_CHECK(timed(prof, VD_PROF_ENERGY, s,
+                   [&] { return launch_energy<T>(energy_of(FV), one_of(FV), 0, s); }));
     return VD_OK;
   }
 
@@ -819,6 +821,174 @@ class Solver final : public ISolver {
   T *dbg_t1_ = nullptr, *dbg_t2_ = nullptr, *dbg_rot_ = nullptr;
 };
 
+// ===========================================================================
+// batched solve: one launch per schedule step over all lattices
+// ===========================================================================
+
+class IBatch {
+ public:
+  virtual ~IBatch() {}
+  virtual int solve(const vd_solve_opts* o, double* energies) = 0;
+};
+
+template <typename T>
+class Batch final : public IBatch {
+ public:
+  enum Kind { kTiles = 0, kNodes = 1, kEnergy = 2, kOne = 3 };
+
+  explicit Batch(std::vector<Solver<T>*> hs) : h_(std::move(hs)) {}
+  ~Batch() override {
+    for (auto& g : exec_)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (capture_) (void)hipStreamDestroy(capture_);
+    pool_.release_all();
+  }
+
+  int init() {
+    n_ = (int)h_.size();
+    L_ = h_[0]->levels();
+    stream_ = h_[0]->stream();
+    graph_ = (h_[0]->desc().flags & VD_FLAG_GRAPH) != 0;
+    // one tile kind per level: that of the largest lattice
+    for (int l = 0; l < L_; ++l) {
+      int big = 0;
+      for (int b = 1; b < n_; ++b)
+        if (h_[b]->level_nodes(l) > h_[big]->level_nodes(l)) big = b;
+      const int kind = h_[big]->level_tile(l);
+      for (int b = 0; b < n_; ++b) h_[b]->force_tile(l, kind);
+    }
+    tables_.resize(L_);
+    for (int l = 0; l < L_; ++l) {
+      VD_CHECK(pool_.alloc(&tables_[l].views, (size_t)n_));
+      for (int k = 0; k < 4; ++k) VD_CHECK(pool_.alloc(&tables_[l].starts[k], (size_t)n_ + 1));
+    }
+    gens_.assign(n_, -1);
+    return VD_OK;
+  }
+
+  int solve(const vd_solve_opts* o, double* energies) override {
+    for (auto* h : h_)
+      if (!h->has_constraints()) return VD_ESTATE;
+    const int reset = (o && o->reset_to_rest) ? 1 : 0;
+    bool stale = false;
+    for (int b = 0; b < n_; ++b) stale |= (gens_[b] != h_[b]->generation());
+    if (stale) {
+      VD_CHECK(build_tables());
+      for (auto& g : exec_)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+    }
+    if (graph_) {
+      if (!exec_[reset]) {
+        if (!capture_) VD_TRY(hipStreamCreateWithFlags(&capture_, hipStreamNonBlocking));
+        VD_TRY(hipStreamSynchronize(stream_));
+        hipGraph_t g = nullptr;
+        VD_TRY(hipStreamBeginCapture(capture_, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue(reset, capture_);
+        const hipError_t e = hipStreamEndCapture(capture_, &g);
+        if (rc != VD_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+        if (e != hipSuccess) return VD_EHIP;
+        const hipError_t ei = hipGraphInstantiate(&exec_[reset], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return VD_EHIP;
+      }
+      VD_TRY(hipGraphLaunch(exec_[reset], stream_));
+    } else {
+      VD_CHECK(enqueue(reset, stream_));
+    }
+    for (auto* h : h_) h->mark_energy_fresh();
+    if (energies) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      for (int b = 0; b < n_; ++b) VD_CHECK(h_[b]->finest_energy_host(energies + 4 * b));
+    }
+    return VD_OK;
+  }
+
+ private:
+  struct Tables {
+    LevelView<T>* views = nullptr;
+    int* starts[4] = {nullptr, nullptr, nullptr, nullptr};
+    int blocks[4] = {0, 0, 0, 0};
+    LevelView<T> first{};
+  };
+
+  // Device tables of the lattices' level views and the first workgroup of
+  // each lattice for every workgroup kind (rebuilt when a handle reallocates).
+  int build_tables() {
+    for (int l = 0; l < L_; ++l) {
+      std::vector<LevelView<T>> views(n_);
+      std::vector<int> st[4];
+      for (int k = 0; k < 4; ++k) st[k].assign(n_ + 1, 0);
+      for (int b = 0; b < n_; ++b) {
+        const LevelView<T> V = h_[b]->level_view(l);
+        views[b] = V;
+        const int cnt[4] = {V.ntiles, node_blocks(V.N), energy_blocks(V.rblocks, V.N), 1};
+        for (int k = 0; k < 4; ++k) st[k][b + 1] = st[k][b] + cnt[k];
+      }
+      Tables& t = tables_[l];
+      t.first = views[0];
+      VD_TRY(hipMemcpy(t.views, views.data(), sizeof(LevelView<T>) * n_, hipMemcpyHostToDevice));
+      for (int k = 0; k < 4; ++k) {
+        VD_TRY(hipMemcpy(t.starts[k], st[k].data(), sizeof(int) * (n_ + 1),
+                         hipMemcpyHostToDevice));
+        t.blocks[k] = st[k][n_];
+      }
+    }
+    for (int b = 0; b < n_; ++b) gens_[b] = h_[b]->generation();
+    return VD_OK;
+  }
+
+  Dispatch<T> D(int l, int kind) const {
+    const Tables& t = tables_[l];
+    Dispatch<T> d{};
+    d.one = t.first;
+    d.views = t.views;
+    d.starts = t.starts[kind];
+    d.n = n_;
+    d.blocks = t.blocks[kind];
+    return d;
+  }
+
+  // The frame schedule of Solver::enqueue_frame with every launch batched.
+  int enqueue(int reset, hipStream_t s) {
+    const int F = L_ - 1;
+    const vd_lattice_desc& dsc = h_[0]->desc();
+    if (reset) VD_TRY(launch_set_rest<T>(D(F, kNodes), s));
+    for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters<T>(D(l, kOne), s));
+    for (int l = 0; l < L_; ++l) {
+      if (l < F) VD_TRY(launch_inject<T>(D(l, kNodes), D(F, kNodes), 1 << (F - l), s));
+      if (l > 0) {
+        VD_TRY(launch_prolong<T>(D(l, kNodes), D(l - 1, kNodes), 1, s));
+        VD_TRY(launch_polar<T>(D(l, kNodes), s));
+      }
+      const int gn = dsc.gn_iters[l], pcg = dsc.pcg_iters[l];
+      for (int k = 0; k < gn; ++k) {
+        VD_TRY(launch_stencil<T>(kModeRhs, D(l, kTiles), nullptr, nullptr, s));
+        for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, D(l, kTiles), s));
+        if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, D(l, kNodes), s));
+        VD_TRY(launch_polar<T>(D(l, kNodes), s));
+      }
+    }
+    VD_TRY(launch_energy<T>(D(F, kEnergy), D(F, kOne), 0, s));
+    return VD_OK;
+  }
+
+  std::vector<Solver<T>*> h_;
+  int n_ = 0, L_ = 0;
+  hipStream_t stream_ = nullptr;
+  hipStream_t capture_ = nullptr;
+  bool graph_ = false;
+  hipGraphExec_t exec_[2] = {nullptr, nullptr};
+  std::vector<Tables> tables_;
+  std::vector<long> gens_;
+  Pool pool_;
+};
+
 }  // namespace vd
 
 // ===========================================================================
@@ -828,6 +998,47 @@ class Solver final : public ISolver {
 struct vd_lattice {
   vd::ISolver* impl;
 };
+
+struct vd_batch {
+  vd::IBatch* impl;
+};
+
+namespace {
+
+template <typename S>
+int make_batch(vd_lattice* const* ls, int n, vd_batch** out) {
+  std::vector<S*> hs;
+  for (int b = 0; b < n; ++b) {
+    S* p = dynamic_cast<S*>(ls[b]->impl);
+    if (!p) return VD_EINVAL;  // mixed precisions
+    hs.push_back(p);
+  }
+  const vd_lattice_desc& d0 = hs[0]->desc();
+  for (S* p : hs) {
+    const vd_lattice_desc& d = p->desc();
+    if (d.num_levels != d0.num_levels || p->stream() != hs[0]->stream()) return VD_EINVAL;
+    for (int l = 0; l < d0.num_levels; ++l)
+      if (d.gn_iters[l] != d0.gn_iters[l] || d.pcg_iters[l] != d0.pcg_iters[l]) return VD_EINVAL;
+  }
+  using T = std::remove_pointer_t<decltype(hs[0]->level_view(0).d)>;
+  auto* bt = new (std::nothrow) vd::Batch<T>(hs);
+  if (!bt) return VD_ENOMEM;
+  const int rc = bt->init();
+  if (rc != VD_OK) {
+    delete bt;
+    return rc;
+  }
+  vd_batch* h = new (std::nothrow) vd_batch;
+  if (!h) {
+    delete bt;
+    return VD_ENOMEM;
+  }
+  h->impl = bt;
+  *out = h;
+  return VD_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -879,6 +1090,29 @@ int vd_lattice_destroy(vd_lattice* l) {
   if (!l) return VD_OK;
   delete l->impl;
   delete l;
+  return VD_OK;
+}
+
+
+int vd_batch_create(vd_lattice* const* ls, int32_t n, vd_batch** out) {
+  if (!ls || !out || n < 1) return VD_EINVAL;
+  *out = nullptr;
+  for (int b = 0; b < n; ++b)
+    if (!ls[b] || !ls[b]->impl) return VD_EINVAL;
+  if (dynamic_cast<vd::Solver<float>*>(ls[0]->impl))
+    return make_batch<vd::Solver<float>>(ls, n, out);
+  return make_batch<vd::Solver<double>>(ls, n, out);
+}
+
+int vd_batch_solve(vd_batch* b, const vd_solve_opts* o, double* energies) {
+  if (!b) return VD_EINVAL;
+  return b->impl->solve(o, energies);
+}
+
+int vd_batch_destroy(vd_batch* b) {
+  if (!b) return VD_OK;
+  delete b->impl;
+  delete b;
   return VD_OK;
 }
 

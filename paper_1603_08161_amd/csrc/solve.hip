@@ -1,0 +1,755 @@
+// The per-frame solve kernels (Sec. 7): gradient, fused CG iterations,
+// rotation fits, energy and level transfers.  Every launch takes a Dispatch:
+// one lattice by value, or a device table of lattices that are all at the
+// same schedule step (the batched solve), with workgroup g belonging to the
+// lattice b for which starts[b] <= g < starts[b + 1].
+//
+// Unknowns are displacements d = t - t_hat; node vectors are SoA [3][N] in
+// x-fastest order (rotations [9][N]).
+
+#include "vd_device.h"
+#include "vd_kernels.h"
+
+namespace vd {
+
+namespace {
+
+inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ bool in_box(int x, int y, int z, int nx, int ny, int nz) {
+  return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+}
+
+__device__ __forceinline__ size_t rot_at(int row, int col, size_t N, size_t i) {
+  return (size_t)(row * 3 + col) * N + i;
+}
+
+// The lattice of workgroup g, its local workgroup index and count.
+template <typename T>
+struct Where {
+  LevelView<T> L;
+  int b, local, count;
+};
+
+template <typename T>
+__device__ __forceinline__ Where<T> locate(const Dispatch<T>& D, int g) {
+  Where<T> w;
+  if (D.n == 1) {
+    w.L = D.one;
+    w.b = 0;
+    w.local = g;
+    w.count = D.blocks;
+    return w;
+  }
+  int lo = 0, hi = D.n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (D.starts[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  w.L = D.views[lo];
+  w.b = lo;
+  w.local = g - D.starts[lo];
+  w.count = D.starts[lo + 1] - D.starts[lo];
+  return w;
+}
+
+template <typename T>
+__device__ __forceinline__ LevelView<T> view_of(const Dispatch<T>& D, int b) {
+  return D.n == 1 ? D.one : D.views[b];
+}
+
+template <typename T>
+__device__ __forceinline__ int energy_blocks_dev(const LevelView<T>& L) {
+  return L.rblocks + (L.N + kBlock - 1) / kBlock;
+}
+
+// Block sums of K values written to out[k * stride + local].
+template <int K>
+__device__ __forceinline__ void write_partials(double (&v)[K], double* out, int stride,
+                                               int local) {
+  __shared__ double lds[K * (kBlock / kWave)];
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[(size_t)k * stride + local] = v[k];
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// tiles
+// ===========================================================================
+
+int tile_blocks(int kind, int nx, int ny, int nz) {
+  auto nb = [&](int tx, int ty, int tz) {
+    return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+  };
+  switch (kind) {
+    case 1: return nb(TileM::TX, TileM::TY, TileM::TZ);
+    case 2: return nb(TileW::TX, TileW::TY, TileW::TZ);
+    default: return nb(TileS::TX, TileS::TY, TileS::TZ);
+  }
+}
+
+int default_tile(int nx, int ny, int nz) { return tile_blocks(1, nx, ny, nz) >= 512 ? 1 : 0; }
+int node_blocks(int N) { return blocks_for(N); }
+int energy_blocks(int rblocks, int N) { return rblocks + blocks_for(N); }
+
+template <typename TL>
+struct TilePos {
+  int x0, y0, z0;  // lattice coordinates of LDS index (0,0,0) (tile origin - 1)
+  __device__ __forceinline__ TilePos(int nx, int ny, int local) {
+    const int ntx = (nx + TL::TX - 1) / TL::TX, nty = (ny + TL::TY - 1) / TL::TY;
+    const int tx = local % ntx, ty = (local / ntx) % nty, tz = local / (ntx * nty);
+    x0 = tx * TL::TX - 1;
+    y0 = ty * TL::TY - 1;
+    z0 = tz * TL::TZ - 1;
+  }
+  // LDS index of the k-th node owned by this thread
+  __device__ __forceinline__ static int own(int k) {
+    const int t = threadIdx.x;
+    const int lx = t % TL::TX + 1, ly = (t / TL::TX) % TL::TY + 1;
+    const int lz = (t / (TL::TX * TL::TY)) * TL::NPT + k + 1;
+    return lx + TL::HX * (ly + TL::HY * lz);
+  }
+};
+
+// ===========================================================================
+// the normal-equation stencil (Sec. 7.1): A p = J^T J p
+// ===========================================================================
+//
+// A p at node i = 2 w_r sum_{j in N_i} (p_i - p_j)                (ARAP part)
+//               + sum_{delta in {-1,0,1}^3} A27_i[delta] p_{i+delta}  (data part)
+//
+// One workgroup per tile; the tile plus a one-node halo of p is staged in LDS
+// (all 27 stencil neighbours of a tile node are in it; nodes outside the
+// lattice hold 0 and have zero blocks).
+
+template <typename T, typename TL>
+__device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
+                                         int gx, int gy, int gz, size_t i, T& o0, T& o1,
+                                         T& o2) {
+  const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
+  T l0 = T(0), l1 = T(0), l2 = T(0);
+  const int off[3] = {1, TL::HX, TL::HX * TL::HY};
+  const int pos[3] = {gx, gy, gz};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (pos[ax] > 0) {
+      const int q = c - off[ax];
+      l0 += p0 - sp[0][q];
+      l1 += p1 - sp[1][q];
+      l2 += p2 - sp[2][q];
+    }
+    if (pos[ax] < lim[ax] - 1) {
+      const int q = c + off[ax];
+      l0 += p0 - sp[0][q];
+      l1 += p1 - sp[1][q];
+      l2 += p2 - sp[2][q];
+    }
+  }
+  const T w2 = T(2) * L.wr;
+  o0 = w2 * l0;
+  o1 = w2 * l1;
+  o2 = w2 * l2;
+  const int slot = L.node_slot[i];
+  if (slot >= 0) {
+    const size_t cap = L.capA;
+    const T* __restrict__ A = L.A27 + slot;
+#pragma unroll
+    for (int dl = 0; dl < 27; ++dl) {
+      const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
+      const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
+      const T* __restrict__ blk = A + (size_t)dl * 6 * cap;
+      const T s0 = blk[0], s1 = blk[cap], s2 = blk[2 * cap], s3 = blk[3 * cap],
+              s4 = blk[4 * cap], s5 = blk[5 * cap];
+      const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
+      o0 += s0 * q0 + s1 * q1 + s2 * q2;
+      o1 += s1 * q0 + s3 * q1 + s4 * q2;
+      o2 += s2 * q0 + s4 * q1 + s5 * q2;
+    }
+  }
+}
+
+// kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
+//            gradient J^T r; r = -g is stored (the CG residual r_0).
+// kModeApply / kModeGrad : A p or g written to `out` (test entry points).
+template <typename T, typename TL, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
+                                                    T* __restrict__ out) {
+  __shared__ T sp[3][TL::HALO];
+  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+  const LevelView<T>& L = w.L;
+  const TilePos<TL> t(L.nx, L.ny, w.local);
+  const size_t N = L.N;
+  const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
+  for (int k = threadIdx.x; k < TL::HALO; k += kBlock) {
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    T v0 = T(0), v1 = T(0), v2 = T(0);
+    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+      const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+      v0 = src[i];
+      v1 = src[N + i];
+      v2 = src[2 * N + i];
+    }
+    sp[0][k] = v0;
+    sp[1][k] = v1;
+    sp[2][k] = v2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    T o0, o1, o2;
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o0, o1, o2);
+    if (MODE == kModeApply) {
+      out[i] = o0;
+      out[N + i] = o1;
+      out[2 * N + i] = o2;
+      continue;
+    }
+    // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
+    // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
+    const T* __restrict__ rot = L.rot;
+    T q0 = T(0), q1 = T(0), q2 = T(0);
+    const int pos[3] = {gx, gy, gz};
+    const int lim[3] = {L.nx, L.ny, L.nz};
+    const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const T ci0 = rot[rot_at(0, ax, N, i)], ci1 = rot[rot_at(1, ax, N, i)],
+              ci2 = rot[rot_at(2, ax, N, i)];
+#pragma unroll
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const int pj = pos[ax] + sgn;
+        if (pj < 0 || pj >= lim[ax]) continue;
+        const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+        const T cj0 = rot[rot_at(0, ax, N, j)], cj1 = rot[rot_at(1, ax, N, j)],
+                cj2 = rot[rot_at(2, ax, N, j)];
+        const T s = -T(sgn) * L.h;
+        T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
+        if (ax == 0) u0 += T(2);
+        if (ax == 1) u1 += T(2);
+        if (ax == 2) u2 += T(2);
+        q0 += s * u0;
+        q1 += s * u1;
+        q2 += s * u2;
+      }
+    }
+    const T g0 = o0 - L.bnode[i] + L.wr * q0;
+    const T g1 = o1 - L.bnode[N + i] + L.wr * q1;
+    const T g2 = o2 - L.bnode[2 * N + i] + L.wr * q2;
+    T* __restrict__ dst = (MODE == kModeGrad) ? out : L.r;
+    const T sg = (MODE == kModeGrad) ? T(1) : T(-1);
+    dst[i] = sg * g0;
+    dst[N + i] = sg * g1;
+    dst[2 * N + i] = sg * g2;
+  }
+}
+
+template <typename T, typename TL>
+void launch_stencil_t(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s) {
+  switch (mode) {
+    case kModeRhs: k_stencil<T, TL, kModeRhs><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
+    case kModeApply: k_stencil<T, TL, kModeApply><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
+    default: k_stencil<T, TL, kModeGrad><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
+  }
+}
+
+// The tile kind is common to all lattices of a launch.
+template <typename T>
+hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s) {
+  if (mode != kModeRhs && mode != kModeApply && mode != kModeGrad) return hipErrorInvalidValue;
+  if (D.blocks <= 0) return hipSuccess;
+  switch (D.one.tile) {
+    case 1: launch_stencil_t<T, TileM>(mode, D, pin, out, s); break;
+    case 2: launch_stencil_t<T, TileW>(mode, D, pin, out, s); break;
+    default: launch_stencil_t<T, TileS>(mode, D, pin, out, s); break;
+  }
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// one Jacobi-preconditioned CG iteration per launch (Sec. 7.1, position step)
+// ===========================================================================
+//
+// Iteration m (FIRST: m = 0) reads the block partials S_{m-1} of the
+// previous launch: r^T D^-1 r, p^T A p, (Ap)^T D^-1 r and (Ap)^T D^-1 Ap of
+// iterate m-1.  From them
+//   alpha_{m-1} = rz_{m-1} / p^T A p                    (zero if p^T A p <= 0)
+//   rz_m        = rz_{m-1} - 2 alpha (Ap)^T D^-1 r + alpha^2 (Ap)^T D^-1 Ap
+//   beta_m      = rz_m / rz_{m-1}                       (zero if rz_{m-1} <= 0)
+// (rz_m is r_m^T D^-1 r_m expanded through r_m = r_{m-1} - alpha Ap_{m-1}, so
+// one reduction phase per iteration suffices).  While staging the tile it
+// forms r_m = r_{m-1} - alpha Ap_{m-1}, p_m = D^-1 r_m + beta p_{m-1}, applies
+// d += alpha p_{m-1} to its own nodes, computes Ap_m and writes S_m.  Iterate
+// m keeps r, p, Ap and S in buffer m % 2 of each pair (r_0 in L.r).  The
+// halo inputs are loaded before the scalar reduction so that both latencies
+// overlap.  The last iteration's step is applied by k_cg_final.
+
+template <typename T>
+__device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& beta,
+                                           Scalars* sc, bool count_guard) {
+  double v[4];
+  sum_partials_k<4>(s, n, v);
+  const double rz = v[0], pap = v[1], apdr = v[2], apdap = v[3];
+  const double a = pap > 0.0 ? rz / pap : 0.0;
+  double rz_new = rz - 2.0 * a * apdr + a * a * apdap;
+  if (rz_new < 0.0) rz_new = 0.0;
+  alpha = (T)a;
+  beta = rz > 0.0 ? (T)(rz_new / rz) : T(0);
+  if (count_guard && threadIdx.x == 0 && !(pap > 0.0)) sc->guard_hits += 1;
+}
+
+template <typename T, typename TL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
+  __shared__ T sp[3][TL::HALO];
+  __shared__ T sr[3][TL::HALO];
+  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+  const LevelView<T>& L = w.L;
+  const TilePos<TL> t(L.nx, L.ny, w.local);
+  const size_t N = L.N;
+  const bool odd = (m & 1) != 0;
+  const T* __restrict__ r_in = (FIRST || odd) ? L.r : L.r2;
+  T* __restrict__ r_out = odd ? L.r2 : L.r;
+  const T* __restrict__ p_in = odd ? L.pa : L.pb;
+  T* __restrict__ p_out = odd ? L.pb : L.pa;
+  const T* __restrict__ ap_in = odd ? L.ap : L.ap2;
+  T* __restrict__ ap_out = odd ? L.ap2 : L.ap;
+  const double* s_in = odd ? L.scg0 : L.scg1;
+  double* s_out = odd ? L.scg1 : L.scg0;
+  const T* __restrict__ dinv = L.dinv;
+  // 1. halo inputs into registers
+  T hr[TL::HPT][3], hq[TL::HPT][3], hp[TL::HPT][3], ha[TL::HPT][3];
+  size_t hi[TL::HPT];
+  bool hin[TL::HPT];
+#pragma unroll
+  for (int h = 0; h < TL::HPT; ++h) {
+    const int k = threadIdx.x + h * kBlock;
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    hin[h] = k < TL::HALO && in_box(gx, gy, gz, L.nx, L.ny, L.nz);
+    hi[h] = hin[h] ? gx + (size_t)L.nx * (gy + (size_t)L.ny * gz) : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      hr[h][a] = T(0);
+      hq[h][a] = T(0);
+      hp[h][a] = T(0);
+      ha[h][a] = T(0);
+    }
+    if (hin[h]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t j = a * N + hi[h];
+        hr[h][a] = r_in[j];
+        hq[h][a] = dinv[j];
+        if (!FIRST) {
+          hp[h][a] = p_in[j];
+          ha[h][a] = ap_in[j];
+        }
+      }
+    }
+  }
+  // 2. CG scalars of the previous iterate
+  T alpha = T(0), beta = T(0);
+  if (!FIRST) cg_scalars<T>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  // 3. r_m, p_m into LDS; own nodes also store r_m, p_m and step d
+#pragma unroll
+  for (int h = 0; h < TL::HPT; ++h) {
+    const int k = threadIdx.x + h * kBlock;
+    if (k >= TL::HALO) continue;
+    T p3[3], r3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T r = hr[h][a];
+      if (!FIRST) r -= alpha * ha[h][a];
+      T p = hq[h][a] * r;
+      if (!FIRST) p += beta * hp[h][a];
+      r3[a] = r;
+      p3[a] = p;
+      sp[a][k] = p;
+      sr[a][k] = r;
+    }
+    const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
+    if (hin[h] && lx >= 1 && lx <= TL::TX && ly >= 1 && ly <= TL::TY && lz >= 1 &&
+        lz <= TL::TZ) {
+      T* __restrict__ d = L.d;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const size_t j = a * N + hi[h];
+        p_out[j] = p3[a];
+        if (!FIRST) {
+          r_out[j] = r3[a];
+          d[j] += alpha * hp[h][a];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // 4. A p_m on own nodes and the block partials of S_m
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    T o[3];
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o[0], o[1], o[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const size_t j = a * N + i;
+      ap_out[j] = o[a];
+      const double q = (double)dinv[j], r = (double)sr[a][c], p = (double)sp[a][c];
+      const double ap = (double)o[a];
+      part[0] += r * q * r;
+      part[1] += p * ap;
+      part[2] += ap * q * r;
+      part[3] += ap * q * ap;
+    }
+  }
+  write_partials<4>(part, s_out, w.count, w.local);
+}
+
+// d += alpha p of the last CG iterate (node workgroups).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& L = w.L;
+  const bool odd = (last & 1) != 0;
+  T alpha, beta;
+  cg_scalars<T>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  const int i = w.local * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+  const T* __restrict__ p = odd ? L.pb : L.pa;
+  T* __restrict__ d = L.d;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) d[a * N + i] += alpha * p[a * N + i];
+}
+
+template <typename T, typename TL>
+void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s) {
+  if (m == 0) k_cg<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
+  else k_cg<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+}
+
+template <typename T>
+hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s) {
+  if (D.blocks <= 0) return hipSuccess;
+  switch (D.one.tile) {
+    case 1: launch_cg_t<T, TileM>(m, D, s); break;
+    case 2: launch_cg_t<T, TileW>(m, D, s); break;
+    default: launch_cg_t<T, TileS>(m, D, s); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s) {
+  if (D.blocks <= 0) return hipSuccess;
+  k_cg_final<T><<<D.blocks, kBlock, 0, s>>>(D, last);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// energy, eq. (1): rows (dense and sparse) and ARAP edges, float64 sums
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy(Dispatch<T> D) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& L = w.L;
+  double part[3] = {0.0, 0.0, 0.0};
+  const size_t N = L.N;
+  const T* __restrict__ d = L.d;
+  if (w.local < L.rblocks) {
+    const int row = w.local * kBlock + threadIdx.x;
+    const int rows = L.sc->rows;
+    if (row < rows) {
+      const int cell = L.row_cell[row];
+      const int cnx = L.nx - 1, cny = L.ny - 1;
+      const int cx = cell % cnx, cy = (cell / cnx) % cny, cz = cell / (cnx * cny);
+      const T* __restrict__ f = L.row_f;
+      const T* __restrict__ sn = L.row_sn;
+      const T fx = f[row], fy = f[(size_t)rows + row], fz = f[2 * (size_t)rows + row];
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const size_t m = (cx + (k & 1)) + (size_t)L.nx * ((cy + ((k >> 1) & 1)) +
+                                                          (size_t)L.ny * (cz + (k >> 2)));
+        const T wk = corner_weight<T>(k, fx, fy, fz);
+        s0 += wk * d[m];
+        s1 += wk * d[N + m];
+        s2 += wk * d[2 * N + m];
+      }
+      const T res = sn[row] * s0 + sn[(size_t)rows + row] * s1 + sn[2 * (size_t)rows + row] * s2 -
+                    L.row_rho[row];
+      const double e = (double)res * (double)res;
+      if (row < L.sc->n_dense) part[0] = e; else part[1] = e;
+    }
+  } else {
+    const int i = (w.local - L.rblocks) * kBlock + threadIdx.x;
+    if (i < L.N) {
+      const T* __restrict__ rot = L.rot;
+      const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+      const int pos[3] = {x, y, z};
+      const int lim[3] = {L.nx, L.ny, L.nz};
+      const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+      double acc = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        // (I - R_i) e_ij with e_ij = -s h axis
+        T c0 = -rot[rot_at(0, ax, N, i)], c1 = -rot[rot_at(1, ax, N, i)],
+          c2 = -rot[rot_at(2, ax, N, i)];
+        if (ax == 0) c0 += T(1);
+        if (ax == 1) c1 += T(1);
+        if (ax == 2) c2 += T(1);
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          const int pj = pos[ax] + sgn;
+          if (pj < 0 || pj >= lim[ax]) continue;
+          const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+          const T s = -T(sgn) * L.h;
+          const T e0 = d[i] - d[j] + s * c0;
+          const T e1 = d[N + i] - d[N + j] + s * c1;
+          const T e2 = d[2 * N + i] - d[2 * N + j] + s * c2;
+          acc += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        }
+      }
+      part[2] = (double)L.wr * acc;
+    }
+  }
+  write_partials<3>(part, L.pe, w.count, w.local);
+}
+
+// One workgroup per lattice: sums its energy partials into sc->energy.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy_finalize(Dispatch<T> D1, int record_trace) {
+  const LevelView<T> L = view_of(D1, blockIdx.x);
+  const int n = energy_blocks_dev(L);
+  double v[3];
+  sum_partials_k<3>(L.pe, n, v);
+  if (threadIdx.x == 0) {
+    Scalars* sc = L.sc;
+    sc->energy[0] = v[0] + v[1] + v[2];
+    sc->energy[1] = v[0];
+    sc->energy[2] = v[1];
+    sc->energy[3] = v[2];
+    if (record_trace && sc->n_trace < VD_MAX_TRACE) {
+      sc->trace[sc->n_trace] = sc->energy[0];
+      sc->n_trace += 1;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_energy(const Dispatch<T>& De, const Dispatch<T>& D1, int record_trace,
+                         hipStream_t s) {
+  if (De.blocks <= 0) return hipSuccess;
+  k_energy<T><<<De.blocks, kBlock, 0, s>>>(De);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_energy_finalize<T><<<D1.blocks, kBlock, 0, s>>>(D1, record_trace);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_reset_counters(Dispatch<T> D1) {
+  if (threadIdx.x != 0) return;
+  Scalars* sc = view_of(D1, blockIdx.x).sc;
+  sc->guard_hits = 0;
+  sc->polar_fp64 = 0;
+  sc->polar_keep = 0;
+  sc->n_trace = 0;
+}
+
+template <typename T>
+hipError_t launch_reset_counters(const Dispatch<T>& D1, hipStream_t s) {
+  k_reset_counters<T><<<D1.blocks, 64, 0, s>>>(D1);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// rotation step (Sec. 7.1): M_i = sum_j (t_i - t_j)(t_hat_i - t_hat_j)^T
+// ===========================================================================
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_polar(Dispatch<T> D) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& L = w.L;
+  const int i = w.local * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+  const T* __restrict__ d = L.d;
+  T* rot = L.rot;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const int pos[3] = {x, y, z};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+  const size_t stride[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+  const T di0 = d[i], di1 = d[N + i], di2 = d[2 * N + i];
+  T M[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = T(0);
+  const T h2 = L.h * L.h;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const int pj = pos[ax] + sgn;
+      if (pj < 0 || pj >= lim[ax]) continue;
+      const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+      // (d_i - d_j + e_ij) e_ij^T with e_ij = -s h axis: column ax gets
+      // -s h (d_i - d_j) + h^2 axis
+      const T s = -T(sgn) * L.h;
+      M[0 * 3 + ax] += s * (di0 - d[j]);
+      M[1 * 3 + ax] += s * (di1 - d[N + j]);
+      M[2 * 3 + ax] += s * (di2 - d[2 * N + j]);
+      M[ax * 3 + ax] += h2;
+    }
+  }
+  T Rp[9], R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rp[k] = rot[(size_t)k * N + i];
+  const int code = fit_or_keep<T>(M, Rp, R);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) rot[(size_t)k * N + i] = R[k];
+  if (code == kFitFp64) atomicAdd(&L.sc->polar_fp64, 1);
+  if (code == kFitKeep) atomicAdd(&L.sc->polar_keep, 1);
+}
+
+template <typename T>
+hipError_t launch_polar(const Dispatch<T>& D, hipStream_t s) {
+  if (D.blocks <= 0) return hipSuccess;
+  k_polar<T><<<D.blocks, kBlock, 0, s>>>(D);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// level transfers (Sec. 7.2)
+// ===========================================================================
+
+// Level node (a,b,c) takes the finest node stride*(a,b,c): d, base and R.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_inject(Dispatch<T> D, Dispatch<T> F, int stride) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& Lv = w.L;
+  const int i = w.local * kBlock + threadIdx.x;
+  if (i >= Lv.N) return;
+  const LevelView<T> Fv = view_of(F, w.b);
+  const int x = i % Lv.nx, y = (i / Lv.nx) % Lv.ny, z = i / (Lv.nx * Lv.ny);
+  const size_t f = (size_t)x * stride + (size_t)Fv.nx * ((size_t)y * stride + (size_t)Fv.ny * z * stride);
+  const size_t N = Lv.N, NF = Fv.N;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T v = Fv.d[k * NF + f];
+    Lv.d[k * N + i] = v;
+    Lv.base[k * N + i] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Lv.rot[k * N + i] = Fv.rot[k * NF + f];
+}
+
+template <typename T>
+hipError_t launch_inject(const Dispatch<T>& D, const Dispatch<T>& F, int stride, hipStream_t s) {
+  if (D.blocks <= 0) return hipSuccess;
+  k_inject<T><<<D.blocks, kBlock, 0, s>>>(D, F, stride);
+  return hipGetLastError();
+}
+
+// fine.d (+)= trilinear evaluation of (coarse.d - coarse.base) at the fine
+// rest positions: fine node a sits at coarse coordinate a/2; its cell is
+// clamped to the last coarse cell, so the last fine plane of an even-sized
+// axis is linearly extrapolated (f = 1.5).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Dispatch<T> D, Dispatch<T> C, int add) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& Fl = w.L;
+  const int i = w.local * kBlock + threadIdx.x;
+  if (i >= Fl.N) return;
+  const LevelView<T> Cv = view_of(C, w.b);
+  const int x = i % Fl.nx, y = (i / Fl.nx) % Fl.ny, z = i / (Fl.nx * Fl.ny);
+  const int p[3] = {x, y, z};
+  const int nc[3] = {Cv.nx, Cv.ny, Cv.nz};
+  int cc[3];
+  T f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int c = p[k] >> 1;
+    if (c > nc[k] - 2) c = nc[k] - 2;
+    cc[k] = c;
+    f[k] = T(0.5) * T(p[k]) - T(c);
+  }
+  const size_t NC = Cv.N, NF = Fl.N;
+  const T* __restrict__ cin = Cv.d;
+  const T* __restrict__ cbase = Cv.base;
+  T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const size_t m = (cc[0] + (k & 1)) +
+                     (size_t)Cv.nx * ((cc[1] + ((k >> 1) & 1)) + (size_t)Cv.ny * (cc[2] + (k >> 2)));
+    const T wk = corner_weight<T>(k, f[0], f[1], f[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T inc = cbase ? cin[a * NC + m] - cbase[a * NC + m] : cin[a * NC + m];
+      v[a] += wk * inc;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (add) Fl.d[a * NF + i] += v[a];
+    else Fl.d[a * NF + i] = v[a];
+  }
+}
+
+template <typename T>
+hipError_t launch_prolong(const Dispatch<T>& Dfine, const Dispatch<T>& C, int add, hipStream_t s) {
+  if (Dfine.blocks <= 0) return hipSuccess;
+  k_prolong<T><<<Dfine.blocks, kBlock, 0, s>>>(Dfine, C, add);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set_rest(Dispatch<T> D) {
+  const Where<T> w = locate(D, blockIdx.x);
+  const LevelView<T>& L = w.L;
+  const int i = w.local * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) L.d[k * N + i] = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) L.rot[k * N + i] = (k % 4 == 0) ? T(1) : T(0);
+}
+
+template <typename T>
+hipError_t launch_set_rest(const Dispatch<T>& D, hipStream_t s) {
+  if (D.blocks <= 0) return hipSuccess;
+  k_set_rest<T><<<D.blocks, kBlock, 0, s>>>(D);
+  return hipGetLastError();
+}
+
+#define VD_INSTANTIATE_SOLVE(T)                                                                  \
+  template hipError_t launch_stencil<T>(int, const Dispatch<T>&, const T*, T*, hipStream_t);    \
+  template hipError_t launch_cg<T>(int, const Dispatch<T>&, hipStream_t);                        \
+  template hipError_t launch_cg_final<T>(int, const Dispatch<T>&, hipStream_t);                  \
+  template hipError_t launch_energy<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
+  template hipError_t launch_reset_counters<T>(const Dispatch<T>&, hipStream_t);                 \
+  template hipError_t launch_polar<T>(const Dispatch<T>&, hipStream_t);                          \
+  template hipError_t launch_inject<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
+  template hipError_t launch_prolong<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
+  template hipError_t launch_set_rest<T>(const Dispatch<T>&, hipStream_t);
+
+VD_INSTANTIATE_SOLVE(float)
+VD_INSTANTIATE_SOLVE(double)
+
+}  // namespace vd

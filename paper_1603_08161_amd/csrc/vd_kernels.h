@@ -28,29 +28,55 @@ struct Scalars {
   double trace[VD_MAX_TRACE];
 };
 
-// Per-level view passed to kernels by value.
+// Per-level view of one lattice, passed to kernels by value (or read from a
+// device table when a launch covers several lattices).
 template <typename T>
 struct LevelView {
   int nx, ny, nz;
   int N;            // nx * ny * nz
   int tile;         // tile kind of the stencil / CG kernels
+  int ntiles;       // workgroups of that tile kind (= CG block partials)
+  int rblocks;      // energy row workgroups (sized by the row capacity)
   T h;              // node spacing of this level
   T wr;             // w_arap
   // node vectors, SoA [3][N] (rot: [9][N], row-major entries)
   T* d;       // displacement t - t_hat (the unknowns)
-  T* r;       // CG residual (= -gradient after the gradient pass)
-  T* ap;      // A p
+  T* r;       // CG residual r_0 (= -gradient) and even iterates
+  T* r2;      // odd CG iterates
+  T* pa;      // CG directions, even / odd iterates
+  T* pb;
+  T* ap;      // A p, even / odd iterates
+  T* ap2;
   T* dinv;    // Jacobi preconditioner 1 / diag(A)
   T* bnode;   // J^T (weighted targets) of the data rows, per node
   T* base;    // finest state injected to this level (for the increment)
   T* rot;     // rotations
+  double* scg0;  // CG block partials [4][ntiles], even / odd iterates
+  double* scg1;
+  double* pe;    // energy block partials [3][rblocks + node blocks]
   // constraint cache
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
   const int* node_slot; // node -> slot in A27, -1 if no data term touches it
   const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
   int capA;             // slots allocated in A27
+  // constraint rows of the current frame (SoA with stride sc->rows)
+  const int* row_cell;
+  const T* row_f;
+  const T* row_sn;
+  const T* row_rho;
   Scalars* sc;
+};
+
+// One launch over one or several lattices (all at the same schedule step).
+// Workgroup g belongs to lattice b with starts[b] <= g < starts[b + 1].
+template <typename T>
+struct Dispatch {
+  LevelView<T> one;           // the lattice when n == 1
+  const LevelView<T>* views;  // device table of n views when n > 1
+  const int* starts;          // device [n + 1] first workgroup of each lattice
+  int n;
+  int blocks;                 // total workgroups
 };
 
 // Constraint rows of one level (dense rows then 3 rows per sparse pair).
@@ -104,70 +130,79 @@ template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
                                  const int* scan, int* node_slot, T* A27, hipStream_t s);
 
-// ---- solve ---------------------------------------------------------------
+// ---- solve (solve.hip) ------------------------------------------------------
 enum StencilMode { kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
 
-// Workgroups (= block partials) of the stencil and CG kernels for a tile kind
-// (0: 8x8x4, 1: 8x8x8, 2: 32x8x4), and the kind used when none is chosen.
+// Workgroups of the stencil and CG kernels for a tile kind (0: 8x8x4,
+// 1: 8x8x8, 2: 32x8x4), the kind used when none is chosen, and the
+// workgroups of the node-parallel and energy kernels.
 int tile_blocks(int kind, int nx, int ny, int nz);
 int default_tile(int nx, int ny, int nz);
-int update_blocks(int N);
-int energy_blocks(int cap_rows, int N);
+int node_blocks(int N);
+int energy_blocks(int rblocks, int N);
 
-// Gradient pass (r = -J^T r into L.r) or the test entry points A p / J^T r.
+// All launchers take a Dispatch whose `blocks`/`starts` were built for the
+// kernel's kind of workgroup: tiles (stencil, CG), nodes (CG final step,
+// rotations, transfers, rest state), rows+nodes (energy) or one per lattice
+// (energy finalize, counters).
+
+// Gradient pass (r = -J^T r into L.r) or the test entry points A p / J^T r
+// (n == 1 only; pin / out are SoA [3][N]).
 template <typename T>
-hipError_t launch_stencil(int mode, const LevelView<T>& L, const T* pin, T* out, hipStream_t s);
+hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s);
 
-// Buffers of one fused CG iteration (see k_cg).
+// CG iteration m (first: m == 0) on every lattice of D (tile workgroups).
 template <typename T>
-struct CgIo {
-  const T* r_in;
-  T* r_out;
-  const T* p_in;
-  T* p_out;
-  const T* ap_in;
-  T* ap_out;
-  const double* s_in;
-  int n_in;
-  double* s_out;
-};
+hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s);
 
+// d += alpha p of CG iterate `last` (node workgroups).
 template <typename T>
-hipError_t launch_cg(bool first, const LevelView<T>& L, const CgIo<T>& io, hipStream_t s);
+hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s);
 
+// Energy of eq. (1) into each lattice's sc->energy (rows+nodes workgroups for
+// De, one workgroup per lattice for D1).
 template <typename T>
-hipError_t launch_cg_final(const LevelView<T>& L, const T* p, const double* s_last, int n,
-                           hipStream_t s);
+hipError_t launch_energy(const Dispatch<T>& De, const Dispatch<T>& D1, int record_trace,
+                         hipStream_t s);
 
-// Energy over the rows (count read from sc->rows; grid sized by `cap_rows`)
-// and the ARAP edges of level L; block partials go to part[3][energy_blocks],
-// then one block sums them into sc->energy (and the trace).
+// Per-frame counters back to zero (one workgroup per lattice).
 template <typename T>
-hipError_t launch_energy(const LevelView<T>& L, const RowView<T>& R, int cap_rows,
-                         double* part, int record_trace, hipStream_t s);
+hipError_t launch_reset_counters(const Dispatch<T>& D1, hipStream_t s);
 
-// Per-frame counters of a level back to zero; rows/n_dense stored when >= 0.
-hipError_t launch_reset_counters(Scalars* sc, int rows, int n_dense, int clear_trace,
-                                 hipStream_t s);
+// Rotation step on every lattice of D (node workgroups), in place.
+template <typename T>
+hipError_t launch_polar(const Dispatch<T>& D, hipStream_t s);
+
+// Level <- finest injection (node workgroups of the level; F: finest views).
+template <typename T>
+hipError_t launch_inject(const Dispatch<T>& D, const Dispatch<T>& F, int stride, hipStream_t s);
+
+// fine.d (+)= prolongation of (coarse.d - coarse.base) (node workgroups of the
+// fine level; C: coarse views, base may be null).
+template <typename T>
+hipError_t launch_prolong(const Dispatch<T>& Dfine, const Dispatch<T>& C, int add, hipStream_t s);
+
+// d = 0, R = I (node workgroups).
+template <typename T>
+hipError_t launch_set_rest(const Dispatch<T>& D, hipStream_t s);
+
+// Single-lattice Dispatch of a view for a given workgroup count.
+template <typename T>
+inline Dispatch<T> single(const LevelView<T>& L, int blocks) {
+  Dispatch<T> D{};
+  D.one = L;
+  D.views = nullptr;
+  D.starts = nullptr;
+  D.n = 1;
+  D.blocks = blocks;
+  return D;
+}
 
 // flags |= 1 where any of the n floats is not finite.
 hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s);
 
-template <typename T>
-hipError_t launch_polar(const LevelView<T>& L, const T* d_in, const T* rot_prev, T* rot_out,
-                        hipStream_t s);
-
-template <typename T>
-hipError_t launch_inject(const LevelView<T>& fine, const LevelView<T>& lvl, int stride,
-                         hipStream_t s);
-
-template <typename T>
-hipError_t launch_prolong_add(const LevelView<T>& coarse, const LevelView<T>& fine,
-                              const T* coarse_in, const T* coarse_base, T* fine_out, int add,
-                              hipStream_t s);
-
-template <typename T>
-hipError_t launch_set_rest(const LevelView<T>& L, hipStream_t s);
+// sc->rows, sc->n_dense of the current frame.
+hipError_t launch_set_counts(Scalars* sc, int rows, int n_dense, hipStream_t s);
 
 template <typename T>
 hipError_t launch_state_io(const LevelView<T>& L, const double* origin, float* pos, float* rot,

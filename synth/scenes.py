@@ -381,3 +381,105 @@ def make_sequence_frame(seed: int, frame: int, n: int = 64, num_levels: int = 3,
     centres = c0 + frame * speed_voxels * h * dirs
     return make_config1(seed=seed, n=n, num_levels=num_levels, gn=gn, pcg=pcg,
                         n_sparse=n_sparse, rbf_centres_override=centres)
+
+
+# ---------------------------------------------------------------------------
+# configuration 2: a batch of uneven lattices, each with its own 320x240 frame
+# ---------------------------------------------------------------------------
+
+CAM2 = dict(width=320, height=240, fx=262.5, fy=262.5, cx=160.0, cy=120.0)
+
+
+def _sphere_points(rng, n_pts, radius, noise_amp):
+    """Fibonacci-sphere points with a smooth random radial perturbation."""
+    k = np.arange(n_pts) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / n_pts)
+    th = np.pi * (1.0 + 5.0 ** 0.5) * k
+    u = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    eta = np.zeros(n_pts)
+    for _ in range(5):
+        a = _random_directions(rng, 1)[0]
+        eta += rng.normal() * np.sin(3.0 * (u @ a) + rng.uniform(0, 2 * np.pi))
+    eta *= noise_amp / max(np.abs(eta).max(), 1e-12)
+    return (radius + eta)[:, None] * u
+
+
+def make_batch_lattice(seed: int, n: int, target_valid: int, n_sparse: int,
+                       num_levels: int = 3, gn: int = 8, pcg: int = 20) -> Scene:
+    """One member of the batched workload: an n^3 lattice around a noisy torus
+    or sphere rendered into a 320x240 depth map (fx = fy = 262.5) with about
+    ``target_valid`` valid pixels, warped by 16 RBFs (amplitude 1.5 node
+    spacings, width n/4 spacings), depth noise 0.05 spacings."""
+    rng = np.random.default_rng(seed)
+    torus = rng.uniform() < 0.5
+    if torus:
+        major = rng.uniform(0.2, 0.3)
+        minor = rng.uniform(0.3, 0.45) * major
+        ext = major + minor
+        area = 4.0 * np.pi * major * minor * np.cos(np.deg2rad(30.0))
+    else:
+        ext = rng.uniform(0.2, 0.35)
+        area = np.pi * ext ** 2
+    nc = n
+    for _ in range(num_levels - 1):
+        nc = (nc + 1) // 2
+    span = 2.0 * 1.12 * ext
+    h = span / ((nc - 1) * 2 ** (num_levels - 1))
+    depth = CAM2["fx"] * np.sqrt(area / target_valid)
+    centre = np.array([0.0, 0.0, depth])
+    origin = centre - 0.5 * span
+    spec = LatticeSpec(dims=(n, n, n), spacing=h, origin=tuple(origin.tolist()),
+                       num_levels=num_levels, gn_iters=(gn,) * num_levels,
+                       pcg_iters=(pcg,) * num_levels)
+    if torus:
+        local = _torus_points(rng, 1200, 500, major, minor, 0.5 * h)
+        local = local @ _rot_x(30.0).T
+    else:
+        local = _sphere_points(rng, 600_000, ext, 0.5 * h)
+    centres = centre[None, :] + rng.uniform(-ext, ext, size=(16, 3))
+    amps = 1.5 * h * _random_directions(rng, 16)
+    warp = RBFWarp(centres, amps, sigma=0.25 * n * h)
+    for attempt in range(2):
+        canon = local + centre[None, :]
+        warped = warp.apply(canon)
+        clean, noisy, winner = _render(warped, CAM2, 0.05 * h, rng)
+        nrm, ok = _depth_normals(clean, CAM2, max_jump=4.0 * h)
+        ok &= noisy > 0
+        count = int(ok.sum())
+        if attempt == 0 and count > 0:
+            # move the camera so that the valid-pixel count nears the target
+            scale = np.sqrt(count / target_valid)
+            shift = depth * (scale - 1.0)
+            centre = centre + np.array([0.0, 0.0, shift])
+            origin = origin + np.array([0.0, 0.0, shift])
+            centres = centres + np.array([0.0, 0.0, shift])
+            depth += shift
+            warp = RBFWarp(centres, amps, sigma=0.25 * n * h)
+            spec.origin = tuple(origin.tolist())
+    vv, uu = np.nonzero(ok)
+    P = _backproject(noisy, CAM2)
+    target = P[vv, uu]
+    normal = nrm[vv, uu]
+    p_hat = canon[winner[vv, uu]]
+    pick = rng.choice(p_hat.shape[0], size=min(n_sparse, p_hat.shape[0]), replace=False)
+    sp_canon = p_hat[pick]
+    sp_target = warp.apply(sp_canon) + rng.normal(scale=0.05 * h, size=sp_canon.shape)
+    return Scene(spec=spec, canon=p_hat.astype(np.float32), target=target.astype(np.float32),
+                 normal=normal.astype(np.float32),
+                 weight=np.ones(p_hat.shape[0], np.float32),
+                 sparse_canon=sp_canon.astype(np.float32),
+                 sparse_target=sp_target.astype(np.float32),
+                 meta={"config": 2, "seed": seed, "shape": "torus" if torus else "sphere",
+                       "valid_pixels": int(p_hat.shape[0]), "target_valid": target_valid})
+
+
+def make_config2(seed: int = 0, count: int = 32, n_range=(24, 64), valid_range=(5000, 60000),
+                 sparse_range=(100, 400)):
+    """The batched workload: ``count`` lattices with node counts per axis drawn
+    uniformly from ``n_range``, each with its own seeded surface and frame."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=count)
+    valid = rng.integers(valid_range[0], valid_range[1] + 1, size=count)
+    sparse = rng.integers(sparse_range[0], sparse_range[1] + 1, size=count)
+    return [make_batch_lattice(1000 * seed + k, int(ns[k]), int(valid[k]), int(sparse[k]))
+            for k in range(count)]

@@ -1,0 +1,80 @@
+"""The batched solve (vd_batch_*): several uneven lattices advanced by one
+launch per schedule step.  Each lattice's arithmetic is that of its own
+single-lattice solve (same tiles, same per-lattice reduction order), so the
+batch must reproduce the individual solves bit for bit, and match the oracle's
+replica solve."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth.scenes import make_batch_lattice
+
+from helpers import make_lattice, rotation_angle
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(12, 3000, 40), (21, 6000, 80), (17, 2500, 30), (30, 9000, 120), (14, 4000, 60)]
+
+
+def _scenes(gn=3, pcg=8):
+    return [make_batch_lattice(500 + k, n, v, s, gn=gn, pcg=pcg)
+            for k, (n, v, s) in enumerate(SIZES)]
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batch_equals_individual_solves(tile):
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes()
+    kw = {"tiles": (tile, tile, tile)}
+    lats = [make_lattice(s, **kw) for s in scenes]
+    batch = Batch(lats)
+    E_batch = batch.solve(reset=True, energies=True)
+    for s, lat, e in zip(scenes, lats, E_batch):
+        ref = make_lattice(s, **kw)
+        rep = ref.solve_frame(reset=True, report=True)
+        np.testing.assert_array_equal(e, rep["energy"])
+        np.testing.assert_array_equal(lat.get_state()[0], ref.get_state()[0])
+        np.testing.assert_array_equal(lat.get_energy(), rep["energy"])
+
+
+def test_batch_matches_oracle():
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes()
+    lats = [make_lattice(s) for s in scenes]
+    E = Batch(lats).solve(reset=True, energies=True)
+    for k in (0, 3):
+        ref = oracle.solve_frame(scenes[k])
+        assert abs(E[k][0] / ref["energy"][0] - 1.0) < 1e-4
+        pos, rot = lats[k].get_state()
+        assert np.abs(pos - ref["t"]).max() / scenes[k].spec.spacing < 1e-3
+        assert rotation_angle(rot, ref["R"]).max() < 1e-2
+
+
+def test_batch_graph_replay_equals_eager_and_sequence():
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes(gn=2, pcg=6)
+    eager = [make_lattice(s) for s in scenes]
+    graph = [make_lattice(s, graph=True) for s in scenes]
+    be, bg = Batch(eager), Batch(graph)
+    for frame in range(3):
+        # frame 0 from rest, later frames continue from the previous state
+        e1 = be.solve(reset=(frame == 0), energies=True)
+        e2 = bg.solve(reset=(frame == 0), energies=True)
+        np.testing.assert_array_equal(e1, e2)
+    for a, b in zip(eager, graph):
+        np.testing.assert_array_equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_batch_rejects_mismatched_handles():
+    from paper_1603_08161_amd import Batch, VDError, VD_EINVAL, Lattice
+    scenes = _scenes()
+    a = make_lattice(scenes[0])
+    b = make_lattice(make_batch_lattice(77, 12, 2000, 20, gn=4, pcg=8))  # other schedule
+    with pytest.raises(VDError) as ei:
+        Batch([a, b])
+    assert ei.value.code == VD_EINVAL
+    c = make_lattice(scenes[1], precision="fp64")
+    with pytest.raises(VDError) as ei:
+        Batch([a, c])
+    assert ei.value.code == VD_EINVAL
