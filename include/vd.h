@@ -194,6 +194,12 @@ int vd_batch_create(vd_lattice* const* lattices, int32_t n, vd_batch** out);
  * the first handle was created with VD_FLAG_GRAPH. */
 int vd_batch_solve(vd_batch* b, const vd_solve_opts* opts, double* energies);
 
+/* Mean duration (us) and count of the finest level's launches per kernel
+ * class (VD_PROF_*) of the last batch frame, when the first handle was
+ * created with VD_FLAG_PROFILE and without VD_FLAG_GRAPH (zeros otherwise).
+ * Call after the frame finished (e.g. after vd_batch_solve with energies). */
+int vd_batch_profile(vd_batch* b, double prof_us[VD_PROF_KINDS], int32_t prof_n[VD_PROF_KINDS]);
+
 /* Free the batch (not the handles).  NULL is a no-op. */
 int vd_batch_destroy(vd_batch* b);
 

@@ -40,7 +40,7 @@ EXPORTED = (
     "vd_get_energy", "vd_get_state", "vd_set_state", "vd_level_info", "vd_strerror",
     "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
     "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong", "vd_tune",
-    "vd_batch_create", "vd_batch_solve", "vd_batch_destroy",
+    "vd_batch_create", "vd_batch_solve", "vd_batch_destroy", "vd_batch_profile",
 )
 
 
@@ -126,6 +126,7 @@ def _load() -> C.CDLL:
         "vd_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
         "vd_batch_solve": ([vp, C.POINTER(SolveOpts), dp], C.c_int),
         "vd_batch_destroy": ([vp], C.c_int),
+        "vd_batch_profile": ([vp, dp, C.POINTER(C.c_int32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -381,6 +382,13 @@ class Batch:
         out = (C.c_double * (4 * len(self.lattices)))()
         _check(_lib.vd_batch_solve(self._h, C.byref(o), out), "vd_batch_solve")
         return np.array(out[:]).reshape(-1, 4)
+
+    def profile(self):
+        """Mean us per finest-level launch by kernel class (profiled batches)."""
+        us = (C.c_double * VD_PROF_KINDS)()
+        n = (C.c_int32 * VD_PROF_KINDS)()
+        _check(_lib.vd_batch_profile(self._h, us, n), "vd_batch_profile")
+        return {PROF_NAMES[k]: float(us[k]) for k in range(len(PROF_NAMES)) if n[k] > 0}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -63,6 +63,57 @@ class Pool {
   std::vector<void*> ptrs_;
 };
 
+// HIP-event timing of launches by kernel class (VD_FLAG_PROFILE).
+class EventTimer {
+ public:
+  ~EventTimer() {
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+  }
+  void reset() {
+    recs_.clear();
+    used_ = 0;
+  }
+  // Runs `launch` (returning hipError_t); when `on`, brackets it with a pair
+  // of events attributed to kernel class `kind`.
+  template <typename F>
+  int timed(bool on, int kind, hipStream_t s, F&& launch) {
+    if (!on) return launch() == hipSuccess ? VD_OK : VD_EHIP;
+    while (pool_.size() < used_ + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return VD_EHIP;
+      pool_.push_back(e);
+    }
+    const int a = (int)used_, b = (int)used_ + 1;
+    used_ += 2;
+    if (hipEventRecord(pool_[a], s) != hipSuccess) return VD_EHIP;
+    if (launch() != hipSuccess) return VD_EHIP;
+    if (hipEventRecord(pool_[b], s) != hipSuccess) return VD_EHIP;
+    recs_.push_back(Rec{kind, a, b});
+    return VD_OK;
+  }
+  // Mean microseconds and launch counts per kind (after the stream drained).
+  int collect(double* us, int* n) const {
+    double sum[VD_PROF_KINDS] = {0};
+    for (int k = 0; k < VD_PROF_KINDS; ++k) n[k] = 0;
+    for (const Rec& r : recs_) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, pool_[r.a], pool_[r.b]) != hipSuccess) return VD_EHIP;
+      sum[r.kind] += 1000.0 * ms;
+      n[r.kind] += 1;
+    }
+    for (int k = 0; k < VD_PROF_KINDS; ++k) us[k] = n[k] ? sum[k] / n[k] : 0.0;
+    return VD_OK;
+  }
+
+ private:
+  struct Rec {
+    int kind, a, b;
+  };
+  std::vector<hipEvent_t> pool_;
+  size_t used_ = 0;
+  std::vector<Rec> recs_;
+};
+
 template <typename T>
 struct LevelData {
   int nx = 0, ny = 0, nz = 0, N = 0, ncell = 0;
@@ -156,7 +207,6 @@ class Solver final : public ISolver {
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     if (h_flags_) (void)hipHostFree(h_flags_);
     if (h_sc_) (void)hipHostFree(h_sc_);
-    for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
     pool_.release_all();
   }
 
@@ -305,15 +355,9 @@ class Solver final : public ISolver {
       }
       if (rep->polar_fp64) rep->bits |= VD_REPORT_POLAR_FP64;
       if (rep->polar_keep) rep->bits |= VD_REPORT_POLAR_KEEP;
-      double sum[VD_PROF_KINDS] = {0};
-      for (const Timed& t : prof_) {
-        float ms = 0.0f;
-        VD_TRY(hipEventElapsedTime(&ms, ev_pool_[t.a], ev_pool_[t.b]));
-        sum[t.kind] += 1000.0 * ms;
-        rep->prof_n[t.kind] += 1;
-      }
-      for (int k = 0; k < VD_PROF_KINDS; ++k)
-        rep->prof_us[k] = rep->prof_n[k] ? sum[k] / rep->prof_n[k] : 0.0;
+      int pn[VD_PROF_KINDS];
+      VD_CHECK(timer_.collect(rep->prof_us, pn));
+      for (int k = 0; k < VD_PROF_KINDS; ++k) rep->prof_n[k] = pn[k];
     }
     return VD_OK;
   }
@@ -576,8 +620,7 @@ class Solver final : public ISolver {
     const double wr = desc_.w_arap;
     const bool trace = (desc_.flags & VD_FLAG_TRACE) != 0;
     const bool prof = (desc_.flags & VD_FLAG_PROFILE) && !(desc_.flags & VD_FLAG_GRAPH);
-    prof_.clear();
-    ev_used_ = 0;
+    timer_.reset();
     const LevelView<T> FV = finest().view(wr);
     if (reset) VD_TRY(launch_set_rest<T>(nodes_of(FV), s));
     for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters<T>(one_of(lv_[l].view(wr)), s));
@@ -612,23 +655,9 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
-  // Runs `launch` (returning hipError_t); when `on`, brackets it with a pair
-  // of timing events attributed to kernel class `kind`.
   template <typename F>
   int timed(bool on, int kind, hipStream_t s, F&& launch) {
-    if (!on) return launch() == hipSuccess ? VD_OK : VD_EHIP;
-    while (ev_pool_.size() < ev_used_ + 2) {
-      hipEvent_t e;
-      VD_TRY(hipEventCreate(&e));
-      ev_pool_.push_back(e);
-    }
-    const int a = (int)ev_used_, b = (int)ev_used_ + 1;
-    ev_used_ += 2;
-    VD_TRY(hipEventRecord(ev_pool_[a], s));
-    if (launch() != hipSuccess) return VD_EHIP;
-    VD_TRY(hipEventRecord(ev_pool_[b], s));
-    prof_.push_back(Timed{kind, a, b});
-    return VD_OK;
+    return timer_.timed(on, kind, s, launch);
   }
 
   int run_graph(int reset) {
@@ -809,13 +838,7 @@ class Solver final : public ISolver {
   int rows_ = 0, n_dense_ = 0;
   bool have_constraints_ = false;
   bool energy_fresh_ = false;
-  // timing events of the last profiled frame
-  struct Timed {
-    int kind, a, b;
-  };
-  std::vector<hipEvent_t> ev_pool_;
-  size_t ev_used_ = 0;
-  std::vector<Timed> prof_;
+  EventTimer timer_;  // timing of the last profiled frame
   // test scratch
   float* dbg_f_ = nullptr;
   T *dbg_t1_ = nullptr, *dbg_t2_ = nullptr, *dbg_rot_ = nullptr;
@@ -829,6 +852,7 @@ class IBatch {
  public:
   virtual ~IBatch() {}
   virtual int solve(const vd_solve_opts* o, double* energies) = 0;
+  virtual int profile(double* us, int* n) = 0;
 };
 
 template <typename T>
@@ -849,6 +873,7 @@ class Batch final : public IBatch {
     L_ = h_[0]->levels();
     stream_ = h_[0]->stream();
     graph_ = (h_[0]->desc().flags & VD_FLAG_GRAPH) != 0;
+    prof_ = !graph_ && (h_[0]->desc().flags & VD_FLAG_PROFILE) != 0;
     // one tile kind per level: that of the largest lattice
     for (int l = 0; l < L_; ++l) {
       int big = 0;
@@ -954,27 +979,43 @@ class Batch final : public IBatch {
     return d;
   }
 
+  int profile(double* us, int* n) override { return timer_.collect(us, n); }
+
   // The frame schedule of Solver::enqueue_frame with every launch batched.
   int enqueue(int reset, hipStream_t s) {
     const int F = L_ - 1;
     const vd_lattice_desc& dsc = h_[0]->desc();
+    timer_.reset();
     if (reset) VD_TRY(launch_set_rest<T>(D(F, kNodes), s));
     for (int l = 0; l < L_; ++l) VD_TRY(launch_reset_counters<T>(D(l, kOne), s));
     for (int l = 0; l < L_; ++l) {
+      const bool on = prof_ && l == F;
       if (l < F) VD_TRY(launch_inject<T>(D(l, kNodes), D(F, kNodes), 1 << (F - l), s));
       if (l > 0) {
-        VD_TRY(launch_prolong<T>(D(l, kNodes), D(l - 1, kNodes), 1, s));
-        VD_TRY(launch_polar<T>(D(l, kNodes), s));
+        VD_CHECK(timer_.timed(on, VD_PROF_TRANSFER, s, [&] {
+          return launch_prolong<T>(D(l, kNodes), D(l - 1, kNodes), 1, s);
+        }));
+        VD_CHECK(timer_.timed(on, VD_PROF_ROTATION, s,
+                              [&] { return launch_polar<T>(D(l, kNodes), s); }));
       }
       const int gn = dsc.gn_iters[l], pcg = dsc.pcg_iters[l];
       for (int k = 0; k < gn; ++k) {
-        VD_TRY(launch_stencil<T>(kModeRhs, D(l, kTiles), nullptr, nullptr, s));
-        for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, D(l, kTiles), s));
-        if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, D(l, kNodes), s));
-        VD_TRY(launch_polar<T>(D(l, kNodes), s));
+        VD_CHECK(timer_.timed(on, VD_PROF_GRADIENT, s, [&] {
+          return launch_stencil<T>(kModeRhs, D(l, kTiles), nullptr, nullptr, s);
+        }));
+        for (int m = 0; m < pcg; ++m)
+          VD_CHECK(timer_.timed(on, VD_PROF_CG_A, s,
+                                [&] { return launch_cg<T>(m, D(l, kTiles), s); }));
+        if (pcg > 0)
+          VD_CHECK(timer_.timed(on, VD_PROF_CG_B, s,
+                                [&] { return launch_cg_final<T>(pcg - 1, D(l, kNodes), s); }));
+        VD_CHECK(timer_.timed(on, VD_PROF_ROTATION, s,
+                              [&] { return launch_polar<T>(D(l, kNodes), s); }));
       }
     }
-    VD_TRY(launch_energy<T>(D(F, kEnergy), D(F, kOne), 0, s));
+    VD_CHECK(timer_.timed(prof_, VD_PROF_ENERGY, s, [&] {
+      return launch_energy<T>(D(F, kEnergy), D(F, kOne), 0, s);
+    }));
     return VD_OK;
   }
 
@@ -984,6 +1025,8 @@ class Batch final : public IBatch {
   hipStream_t capture_ = nullptr;
   bool graph_ = false;
   hipGraphExec_t exec_[2] = {nullptr, nullptr};
+  bool prof_ = false;
+  EventTimer timer_;
   std::vector<Tables> tables_;
   std::vector<long> gens_;
   Pool pool_;
@@ -1107,6 +1150,11 @@ int vd_batch_create(vd_lattice* const* ls, int32_t n, vd_batch** out) {
 int vd_batch_solve(vd_batch* b, const vd_solve_opts* o, double* energies) {
   if (!b) return VD_EINVAL;
   return b->impl->solve(o, energies);
+}
+
+int vd_batch_profile(vd_batch* b, double* prof_us, int32_t* prof_n) {
+  if (!b || !prof_us || !prof_n) return VD_EINVAL;
+  return b->impl->profile(prof_us, prof_n);
 }
 
 int vd_batch_destroy(vd_batch* b) {
