@@ -82,6 +82,8 @@ extern "C" {
 #define VD_REPORT_POLAR_FP64 2u   /* some rotation fits were redone in float64 */
 #define VD_REPORT_POLAR_KEEP 4u   /* some rotation fits were degenerate and kept
                                      the previous rotation */
+#define VD_REPORT_WARM_REJECTED 8u /* the predicted initialisation had the
+                                      higher energy and was dropped */
 
 #define VD_MAX_LEVELS 4
 #define VD_MAX_TRACE 512
@@ -132,10 +134,28 @@ typedef struct {
   int32_t mem; /* VD_MEM_HOST or VD_MEM_DEVICE for all pointers above */
 } vd_constraints;
 
-/* Per-frame options; a NULL opts means all zero. */
+/* Per-frame options; a NULL opts means all zero.
+ *
+ * Warm start (not in the paper; see vd_net.h for the network that produces
+ * init_delta).  When init_delta is given the call first evaluates eq. (1) at
+ * the plain initialisation (the previous frame's state) and at the predicted
+ * one (finest displacement + spacing * init_delta, followed by one rotation
+ * fit), and keeps the lower of the two.  The solve then runs from the kept
+ * state.  When energy_target > 0 the call runs finest-level flip-flop
+ * iterations only, and stops after the first one whose energy is <=
+ * energy_target, or after max_gn of them; with energy_target == 0 the full
+ * schedule runs.  Target mode waits for the stream after every iteration. */
 typedef struct {
-  int32_t reset_to_rest; /* start from t = t_hat, R = I instead of the
-                            previous frame's state */
+  int32_t reset_to_rest;    /* start from t = t_hat, R = I instead of the
+                               previous frame's state */
+  int32_t init_mem;         /* VD_MEM_HOST or VD_MEM_DEVICE for init_delta */
+  const float* init_delta;  /* NULL or [3][N] (x block, y block, z block)
+                               predicted displacement change, in units of the
+                               finest spacing */
+  double energy_target;     /* > 0: finest-level iterations until E <= it */
+  int32_t max_gn;           /* iteration cap in target mode (0: the finest
+                               level's gn_iters) */
+  int32_t reserved;
 } vd_solve_opts;
 
 /* Filled by vd_solve_frame when a report pointer is given (the call then
@@ -152,6 +172,12 @@ typedef struct {
   double prof_us[VD_PROF_KINDS]; /* VD_FLAG_PROFILE: mean duration (us) of
                                     the finest level's launches per class */
   int32_t prof_n[VD_PROF_KINDS];  /* launches timed per class */
+  double init_energy[2]; /* init_delta given: E_total at the plain and at the
+                            predicted initialisation */
+  int32_t warm_used;     /* 1 if the predicted initialisation was kept */
+  int32_t gn_done;       /* target mode: finest-level iterations run */
+  int32_t target_reached; /* target mode: 1 if E <= energy_target */
+  int32_t reserved;
 } vd_solve_report;
 
 /* Create a handle: allocates every per-level device array and puts the state
@@ -191,7 +217,8 @@ int vd_batch_create(vd_lattice* const* lattices, int32_t n, vd_batch** out);
  * VD_ESTATE if a handle has no constraints.  energies (may be NULL) receives
  * n x 4 values, eq. (1) per lattice, after waiting for the stream; without it
  * the call is asynchronous.  The schedule is replayed from a hipGraph when
- * the first handle was created with VD_FLAG_GRAPH. */
+ * the first handle was created with VD_FLAG_GRAPH.  Only reset_to_rest of
+ * opts applies; a warm start or energy target gives VD_EINVAL. */
 int vd_batch_solve(vd_batch* b, const vd_solve_opts* opts, double* energies);
 
 /* Mean duration (us) and count of the finest level's launches per kernel

@@ -117,10 +117,16 @@ def init_params(rng: np.random.Generator, scale_head: float = 0.1) -> Dict[str, 
     return p
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray):
-    """Network output (3, nz, ny, nx) and the activations needed by backward."""
+def _identity(a):
+    return a
+
+
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, act_round=_identity):
+    """Network output (3, nz, ny, nx) and the activations needed by backward.
+    act_round is applied to every stored activation (e.g. bf16_round to model
+    an implementation that keeps activations in bfloat16)."""
     a = {"x": x}
-    relu = lambda v: np.maximum(v, 0.0)
+    relu = lambda v: act_round(np.maximum(v, 0.0))
     a["e0a"] = relu(conv3d(x, p["e0a.W"], p["e0a.b"]))
     a["e0"] = relu(conv3d(a["e0a"], p["e0.W"], p["e0.b"]))
     a["e1a"] = relu(conv3d(a["e0"], p["e1a.W"], p["e1a.b"], 2))
@@ -139,31 +145,54 @@ def forward(p: Dict[str, np.ndarray], x: np.ndarray):
     return out, a
 
 
-def backward(p: Dict[str, np.ndarray], a, dout: np.ndarray) -> Dict[str, np.ndarray]:
-    """Parameter gradients for the upstream gradient dout of the output."""
+def backward(p: Dict[str, np.ndarray], a, dout: np.ndarray,
+             grad_round=_identity) -> Dict[str, np.ndarray]:
+    """Parameter gradients for the upstream gradient dout of the output.
+    grad_round is applied to dout and to every stored gradient tensor: the
+    gradients w.r.t. pre-activations, the skip parts of the concatenations
+    and the gradients w.r.t. up-sampled tensors."""
     g = {}
+    q = grad_round
 
     def conv_b(name, x_in, dy, stride=1):
         dx, g[name + ".W"], g[name + ".b"] = conv3d_backward(x_in, p[name + ".W"], dy, stride)
         return dx
 
-    relu_b = lambda dy, y: dy * (y > 0)
-    dd0 = conv_b("head", a["d0"], dout)
-    dc0 = conv_b("d0", a["c0"], relu_b(dd0, a["d0"]))
-    du0, de0_skip = dc0[:16], dc0[16:]
-    dup0 = conv_b("u0", a["up0"], relu_b(du0, a["u0"]))
-    dd1 = upsample_backward(dup0, a["d1"].shape[1:])
-    dc1 = conv_b("d1", a["c1"], relu_b(dd1, a["d1"]))
-    du1, de1_skip = dc1[:32], dc1[32:]
-    dup1 = conv_b("u1", a["up1"], relu_b(du1, a["u1"]))
-    de2 = upsample_backward(dup1, a["e2"].shape[1:])
-    de2a = conv_b("e2", a["e2a"], relu_b(de2, a["e2"]))
-    de1 = conv_b("e2a", a["e1"], relu_b(de2a, a["e2a"]), 2) + de1_skip
-    de1a = conv_b("e1", a["e1a"], relu_b(de1, a["e1"]))
-    de0 = conv_b("e1a", a["e0"], relu_b(de1a, a["e1a"]), 2) + de0_skip
-    de0a = conv_b("e0", a["e0a"], relu_b(de0, a["e0"]))
-    g["x"] = conv_b("e0a", a["x"], relu_b(de0a, a["e0a"]))
+    relu_b = lambda dy, y: q(dy * (y > 0))
+    dout = q(dout)
+    g_d0 = relu_b(conv_b("head", a["d0"], dout), a["d0"])
+    dc0 = conv_b("d0", a["c0"], g_d0)
+    g_u0, skip0 = relu_b(dc0[:16], a["u0"]), q(dc0[16:])
+    dup0 = q(conv_b("u0", a["up0"], g_u0))
+    g_d1 = relu_b(upsample_backward(dup0, a["d1"].shape[1:]), a["d1"])
+    dc1 = conv_b("d1", a["c1"], g_d1)
+    g_u1, skip1 = relu_b(dc1[:32], a["u1"]), q(dc1[32:])
+    dup1 = q(conv_b("u1", a["up1"], g_u1))
+    g_e2 = relu_b(upsample_backward(dup1, a["e2"].shape[1:]), a["e2"])
+    g_e2a = relu_b(conv_b("e2", a["e2a"], g_e2), a["e2a"])
+    g_e1 = relu_b(conv_b("e2a", a["e1"], g_e2a, 2) + skip1, a["e1"])
+    g_e1a = relu_b(conv_b("e1", a["e1a"], g_e1), a["e1a"])
+    g_e0 = relu_b(conv_b("e1a", a["e0"], g_e1a, 2) + skip0, a["e0"])
+    g_e0a = relu_b(conv_b("e0", a["e0a"], g_e0), a["e0a"])
+    g["x"] = conv_b("e0a", a["x"], g_e0a)
     return g
+
+
+def flatten(p: Dict[str, np.ndarray]) -> np.ndarray:
+    """Parameters (or gradients) as one vector: per layer W then b."""
+    return np.concatenate([np.concatenate([p[n + ".W"].reshape(-1), p[n + ".b"]])
+                           for n, *_ in LAYERS])
+
+
+def unflatten(v: np.ndarray) -> Dict[str, np.ndarray]:
+    p, o = {}, 0
+    for name, ci, co, _, _ in LAYERS:
+        nw = co * ci * 27
+        p[name + ".W"] = np.asarray(v[o:o + nw], np.float64).reshape(co, ci, 3, 3, 3)
+        p[name + ".b"] = np.asarray(v[o + nw:o + nw + co], np.float64)
+        o += nw + co
+    assert o == v.size
+    return p
 
 
 def mse_loss(out: np.ndarray, target: np.ndarray):

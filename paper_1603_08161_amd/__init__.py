@@ -1,6 +1,7 @@
 """MI355X (gfx950) implementation of the VolumeDeform lattice solve.
 
-The solver lives in the HIP library ``libvd.so`` (C-ABI: ``include/vd.h``);
+The solver and the warm-start network live in the HIP library ``libvd.so``
+(C-ABI: ``include/vd.h``, ``include/vd_net.h``);
 this package is its Python binding.  Importing it loads the library and fails
 loudly if it has not been built.
 """
@@ -10,10 +11,11 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     Batch,
     Lattice,
+    Net,
     VDError,
     fit_rotations,
     lib,
     strerror,
     VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE,
-    VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP,
+    VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP, VD_REPORT_WARM_REJECTED,
 )

@@ -1,4 +1,4 @@
-"""ctypes binding of libvd.so (the C-ABI in include/vd.h).
+"""ctypes binding of libvd.so (the C-ABI in include/vd.h and include/vd_net.h).
 
 Argument marshalling only: every step of the solve runs in the library's HIP
 kernels.  Arrays may be numpy (host memory) or torch CUDA tensors (device
@@ -32,6 +32,7 @@ VD_FLAG_GRAPH, VD_FLAG_TRACE, VD_FLAG_PROFILE = 1, 2, 4
 VD_PROF_KINDS = 8
 PROF_NAMES = ("gradient", "cg_a", "cg_b", "rotation", "energy", "transfer")
 VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
+VD_REPORT_WARM_REJECTED = 8
 VD_MAX_LEVELS = 4
 VD_MAX_TRACE = 512
 
@@ -41,6 +42,9 @@ EXPORTED = (
     "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
     "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong", "vd_tune",
     "vd_batch_create", "vd_batch_solve", "vd_batch_destroy", "vd_batch_profile",
+    "vd_warm_features", "vd_net_param_count", "vd_net_create", "vd_net_destroy",
+    "vd_net_set_params", "vd_net_get_params", "vd_net_forward", "vd_net_gradients",
+    "vd_net_train_step",
 )
 
 
@@ -76,7 +80,14 @@ class Constraints(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("reset_to_rest", C.c_int32)]
+    _fields_ = [
+        ("reset_to_rest", C.c_int32),
+        ("init_mem", C.c_int32),
+        ("init_delta", C.c_void_p),
+        ("energy_target", C.c_double),
+        ("max_gn", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
 
 
 class SolveReport(C.Structure):
@@ -89,6 +100,11 @@ class SolveReport(C.Structure):
         ("trace", C.c_double * VD_MAX_TRACE),
         ("prof_us", C.c_double * VD_PROF_KINDS),
         ("prof_n", C.c_int32 * VD_PROF_KINDS),
+        ("init_energy", C.c_double * 2),
+        ("warm_used", C.c_int32),
+        ("gn_done", C.c_int32),
+        ("target_reached", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -127,6 +143,15 @@ def _load() -> C.CDLL:
         "vd_batch_solve": ([vp, C.POINTER(SolveOpts), dp], C.c_int),
         "vd_batch_destroy": ([vp], C.c_int),
         "vd_batch_profile": ([vp, dp, C.POINTER(C.c_int32)], C.c_int),
+        "vd_warm_features": ([vp, vp, vp, i32], C.c_int),
+        "vd_net_param_count": ([], i64),
+        "vd_net_create": ([i32, i32, i32, i32, vp, C.POINTER(vp)], C.c_int),
+        "vd_net_destroy": ([vp], C.c_int),
+        "vd_net_set_params": ([vp, vp, i32], C.c_int),
+        "vd_net_get_params": ([vp, vp, i32], C.c_int),
+        "vd_net_forward": ([vp, vp, i32, vp, i32], C.c_int),
+        "vd_net_gradients": ([vp, vp, vp, i32, vp, dp, i32], C.c_int),
+        "vd_net_train_step": ([vp, vp, vp, i32, C.c_float, i32, dp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -271,21 +296,64 @@ class Lattice:
         self.set_constraints(scene.canon, scene.target, scene.normal, scene.weight,
                              scene.sparse_canon, scene.sparse_target)
 
-    def solve_frame(self, reset: bool = False, report: bool = False):
+    def solve_frame(self, reset: bool = False, report: bool = False, init_delta=None,
+                    energy_target: float = 0.0, max_gn: int = 0):
+        """Solve one frame.  init_delta ([3][N] float32, units of the finest
+        spacing, numpy or CUDA tensor) asks for the judged warm start;
+        energy_target > 0 runs finest-level iterations until E <= it (at most
+        max_gn, 0 = the schedule's count)."""
         o = SolveOpts()
         o.reset_to_rest = 1 if reset else 0
+        keep = None
+        if init_delta is not None:
+            (ptr,), mem, keep = _prep([init_delta])
+            o.init_delta = ptr
+            o.init_mem = mem
+        o.energy_target = float(energy_target)
+        o.max_gn = int(max_gn)
         if not report:
             _check(_lib.vd_solve_frame(self._h, C.byref(o), None), "vd_solve_frame")
             return None
         r = SolveReport()
         _check(_lib.vd_solve_frame(self._h, C.byref(o), C.byref(r)), "vd_solve_frame")
+        del keep
         return {"energy": np.array(r.energy[:]), "bits": int(r.bits),
                 "polar_fp64": int(r.polar_fp64), "polar_keep": int(r.polar_keep),
                 "trace": np.array(r.trace[:r.n_trace]),
                 "prof_us": {PROF_NAMES[k]: float(r.prof_us[k]) for k in range(len(PROF_NAMES))
                             if r.prof_n[k] > 0},
                 "prof_n": {PROF_NAMES[k]: int(r.prof_n[k]) for k in range(len(PROF_NAMES))
-                           if r.prof_n[k] > 0}}
+                           if r.prof_n[k] > 0},
+                "init_energy": np.array(r.init_energy[:]), "warm_used": int(r.warm_used),
+                "gn_done": int(r.gn_done), "target_reached": int(r.target_reached)}
+
+    def warm_features(self, prev2=None, out=None):
+        """Input features of the warm-start network (vd_warm_features) as
+        [nz][ny][nx][8] bfloat16 bit patterns: a uint16 numpy array, or written
+        into `out` (a contiguous int16 CUDA tensor of 8N elements)."""
+        n = self.n_nodes()
+        if out is not None:
+            if not (_is_device(out) and out.dtype == torch.int16 and out.is_contiguous()
+                    and out.numel() == 8 * n):
+                raise ValueError("out must be a contiguous int16 CUDA tensor of 8N elements")
+            p2 = None
+            if prev2 is not None:
+                (p2,), mem, keep = _prep([prev2])
+                if mem != VD_MEM_DEVICE:
+                    raise ValueError("prev2 must be on the device when out is")
+            _check(_lib.vd_warm_features(self._h, p2, out.data_ptr(), VD_MEM_DEVICE),
+                   "vd_warm_features")
+            return out
+        p2 = None
+        keep = None
+        if prev2 is not None:
+            p2h = _host(prev2)
+            keep = p2h
+            p2 = p2h.ctypes.data
+        x = np.empty(8 * n, np.uint16)
+        _check(_lib.vd_warm_features(self._h, p2, x.ctypes.data, VD_MEM_HOST), "vd_warm_features")
+        del keep
+        return x.reshape(self.level_info(self.num_levels - 1)[0][::-1] + (8,))
 
     def tune(self, iters: int = 10):
         """Run the library's tile autotuner; returns (tiles per level, mean us per
@@ -415,3 +483,95 @@ def fit_rotations(M, R_prev=None, precision: str = "fp32", stream: Optional[int]
                                        VD_FP64 if precision == "fp64" else VD_FP32_FP64RED,
                                        VD_MEM_HOST, C.c_void_p(s)), "vd_debug_fit_rotations")
     return R.reshape(n, 3, 3), code
+
+
+def _bf16_ptr(x, n, what):
+    """(pointer, mem, keepalive) of a bfloat16-bits array of n elements."""
+    if _is_device(x):
+        if x.dtype not in (torch.int16, torch.bfloat16) or not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"{what}: contiguous int16/bfloat16 CUDA tensor of {n} elements")
+        return x.data_ptr(), VD_MEM_DEVICE, x
+    h = np.ascontiguousarray(x, dtype=np.uint16).reshape(-1)
+    if h.size != n:
+        raise ValueError(f"{what}: {n} elements expected, got {h.size}")
+    return h.ctypes.data, VD_MEM_HOST, h
+
+
+class Net:
+    """The warm-start network (vd_net*) for nx*ny*nz grids, up to max_batch
+    samples per call."""
+
+    def __init__(self, dims, max_batch: int = 1, stream: Optional[int] = None):
+        self.dims = tuple(int(d) for d in dims)
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        s = _current_stream() if stream is None else stream
+        _check(_lib.vd_net_create(self.dims[0], self.dims[1], self.dims[2], self.max_batch,
+                                  C.c_void_p(s), C.byref(h)), "vd_net_create")
+        self._h = h
+        self.n = self.dims[0] * self.dims[1] * self.dims[2]
+
+    @staticmethod
+    def param_count() -> int:
+        return int(_lib.vd_net_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.vd_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p) -> None:
+        (ptr,), mem, keep = _prep([p])
+        _check(_lib.vd_net_set_params(self._h, ptr, mem), "vd_net_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.param_count(), np.float32)
+        _check(_lib.vd_net_get_params(self._h, out.ctypes.data, VD_MEM_HOST), "vd_net_get_params")
+        return out
+
+    def forward(self, x, batch: int = 1, out=None):
+        """x: [batch][nz][ny][nx][8] bfloat16 bits; returns [batch][3][N] float32
+        (numpy, or `out` filled for device inputs)."""
+        xp, mem, keep = _bf16_ptr(x, batch * self.n * 8, "x")
+        if mem == VD_MEM_DEVICE:
+            if out is None:
+                out = torch.empty(batch * 3 * self.n, dtype=torch.float32, device=x.device)
+            _check(_lib.vd_net_forward(self._h, xp, batch, out.data_ptr(), mem), "vd_net_forward")
+            return out
+        res = np.empty(batch * 3 * self.n, np.float32)
+        _check(_lib.vd_net_forward(self._h, xp, batch, res.ctypes.data, mem), "vd_net_forward")
+        return res.reshape(batch, 3, self.n)
+
+    def gradients(self, x, target, batch: int = 1):
+        """(loss, gradient) at the current parameters, host arrays."""
+        xp, mem, keep = _bf16_ptr(x, batch * self.n * 8, "x")
+        if mem != VD_MEM_HOST:
+            raise ValueError("gradients() takes host arrays")
+        t = np.ascontiguousarray(target, dtype=np.float32).reshape(-1)
+        g = np.empty(self.param_count(), np.float32)
+        loss = C.c_double()
+        _check(_lib.vd_net_gradients(self._h, xp, t.ctypes.data, batch, g.ctypes.data,
+                                     C.byref(loss), mem), "vd_net_gradients")
+        return float(loss.value), g
+
+    def train_step(self, x, target, batch: int = 1, lr: float = 1e-3, want_loss: bool = False):
+        xp, mem, keep = _bf16_ptr(x, batch * self.n * 8, "x")
+        if mem == VD_MEM_DEVICE:
+            if not (_is_device(target) and target.dtype == torch.float32
+                    and target.is_contiguous() and target.numel() == batch * 3 * self.n):
+                raise ValueError("target: contiguous float32 CUDA tensor of batch*3*N")
+            tp, tk = target.data_ptr(), target
+        else:
+            tk = np.ascontiguousarray(target, dtype=np.float32).reshape(-1)
+            tp = tk.ctypes.data
+        loss = C.c_double()
+        _check(_lib.vd_net_train_step(self._h, xp, tp, batch, float(lr), mem,
+                                      C.byref(loss) if want_loss else None),
+               "vd_net_train_step")
+        return float(loss.value) if want_loss else None

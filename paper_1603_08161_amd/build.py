@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvd.so")
-SOURCES = ["kernels.hip", "solve.hip", "sort.hip", "api.hip"]
+SOURCES = ["kernels.hip", "solve.hip", "sort.hip", "net.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "../../include/vd.h"
+#include "../../include/vd_net.h"
+#include "net_kernels.h"
 #include "vd_device.h"
 #include "vd_kernels.h"
 
@@ -195,6 +197,7 @@ class ISolver {
                               int mem) = 0;
   virtual int debug_prolong(int level, const float* coarse, float* out, int mem) = 0;
   virtual int tune(int iters, int* tile_out, double* us_out) = 0;
+  virtual int warm_features(const float* prev2, uint16_t* x, int mem) = 0;
 };
 
 template <typename T>
@@ -204,6 +207,7 @@ class Solver final : public ISolver {
   ~Solver() override {
     if (graph_exec_[0]) (void)hipGraphExecDestroy(graph_exec_[0]);
     if (graph_exec_[1]) (void)hipGraphExecDestroy(graph_exec_[1]);
+    if (gn_graph_) (void)hipGraphExecDestroy(gn_graph_);
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     if (h_flags_) (void)hipHostFree(h_flags_);
     if (h_sc_) (void)hipHostFree(h_sc_);
@@ -333,8 +337,23 @@ class Solver final : public ISolver {
   // ---------------------------------------------------------------------
   int solve_frame(const vd_solve_opts* o, vd_solve_report* rep) override {
     if (!have_constraints_) return VD_ESTATE;
-    const int reset = (o && o->reset_to_rest) ? 1 : 0;
-    if (desc_.flags & VD_FLAG_GRAPH) {
+    int reset = (o && o->reset_to_rest) ? 1 : 0;
+    const bool warm = o && o->init_delta;
+    const bool target = o && o->energy_target > 0.0;
+    if (o && (!(o->energy_target >= 0.0) || !std::isfinite(o->energy_target) || o->max_gn < 0))
+      return VD_EINVAL;
+    if (warm && o->init_mem != VD_MEM_HOST && o->init_mem != VD_MEM_DEVICE) return VD_EINVAL;
+    double e_init[2] = {0.0, 0.0};
+    int warm_used = 0, gn_done = 0, reached = 0;
+    if (reset && (warm || target)) {
+      VD_TRY(launch_set_rest<T>(nodes_of(finest().view(desc_.w_arap)), stream_));
+      reset = 0;
+    }
+    if (warm) VD_CHECK(apply_warm(o->init_delta, o->init_mem, e_init, &warm_used));
+    if (target) {
+      const int cap = o->max_gn > 0 ? o->max_gn : desc_.gn_iters[L_ - 1];
+      VD_CHECK(run_target(o->energy_target, cap, &gn_done, &reached));
+    } else if (desc_.flags & VD_FLAG_GRAPH) {
       VD_CHECK(run_graph(reset));
     } else {
       VD_CHECK(enqueue_frame(reset, stream_));
@@ -344,6 +363,7 @@ class Solver final : public ISolver {
       std::memset(rep, 0, sizeof(*rep));
       VD_TRY(hipStreamSynchronize(stream_));
       for (int l = 0; l < L_; ++l) {
+        if (target && l != L_ - 1) continue;
         VD_TRY(hipMemcpy(h_sc_, lv_[l].sc, sizeof(Scalars), hipMemcpyDeviceToHost));
         if (h_sc_->guard_hits) rep->bits |= VD_REPORT_PCG_GUARD;
         rep->polar_fp64 += h_sc_->polar_fp64;
@@ -355,9 +375,48 @@ class Solver final : public ISolver {
       }
       if (rep->polar_fp64) rep->bits |= VD_REPORT_POLAR_FP64;
       if (rep->polar_keep) rep->bits |= VD_REPORT_POLAR_KEEP;
+      if (warm && !warm_used) rep->bits |= VD_REPORT_WARM_REJECTED;
+      rep->init_energy[0] = e_init[0];
+      rep->init_energy[1] = e_init[1];
+      rep->warm_used = warm_used;
+      rep->gn_done = gn_done;
+      rep->target_reached = reached;
       int pn[VD_PROF_KINDS];
       VD_CHECK(timer_.collect(rep->prof_us, pn));
       for (int k = 0; k < VD_PROF_KINDS; ++k) rep->prof_n[k] = pn[k];
+    }
+    return VD_OK;
+  }
+
+  // Features of vd_net.h for the coming frame (see vd_warm_features).
+  int warm_features(const float* prev2, uint16_t* x, int mem) override {
+    if (!x || (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE)) return VD_EINVAL;
+    if (!have_constraints_) return VD_ESTATE;
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    VD_CHECK(ensure_debug());
+    const float* p2 = prev2;
+    if (prev2 && mem == VD_MEM_HOST) {
+      VD_TRY(hipMemcpyAsync(dbg_f_, prev2, 12 * N, hipMemcpyHostToDevice, stream_));
+      p2 = dbg_f_;
+    }
+    const size_t need = 2 * (size_t)std::max(n_dense_, 1);
+    if (need > feat_cap_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(feat_scratch_);
+      VD_CHECK(pool_.alloc(&feat_scratch_, need));
+      feat_cap_ = need;
+    }
+    uint16_t* xd = x;
+    if (mem == VD_MEM_HOST) {
+      if (!feat_x_) VD_CHECK(pool_.alloc(&feat_x_, 8 * N));
+      xd = feat_x_;
+    }
+    VD_TRY(net::launch_features<T>(F.view(desc_.w_arap), F.rows_view(rows_, n_dense_), p2,
+                                   feat_scratch_, xd, stream_));
+    if (mem == VD_MEM_HOST) {
+      VD_TRY(hipMemcpyAsync(x, feat_x_, 16 * N, hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
     }
     return VD_OK;
   }
@@ -687,6 +746,108 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
+  // E_total of the finest state (waits for the stream).
+  int finest_energy(double* e) {
+    const LevelView<T> V = finest().view(desc_.w_arap);
+    VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, stream_));
+    VD_TRY(hipMemcpyAsync(h_sc_, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    *e = h_sc_->energy[0];
+    return VD_OK;
+  }
+
+  // Warm start: evaluate eq. (1) at the plain initialisation and at
+  // d + h * delta (after one rotation fit), keep the lower.
+  int apply_warm(const float* delta, int mem, double e[2], int* used) {
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    VD_CHECK(ensure_debug());
+    if (!warm_d_) {
+      VD_CHECK(pool_.alloc(&warm_d_, 3 * N));
+      VD_CHECK(pool_.alloc(&warm_rot_, 9 * N));
+    }
+    const float* dd = delta;
+    if (mem == VD_MEM_HOST) {
+      VD_TRY(hipMemcpyAsync(dbg_f_, delta, 12 * N, hipMemcpyHostToDevice, stream_));
+      dd = dbg_f_;
+    }
+    VD_TRY(hipMemsetAsync(d_flags_, 0, sizeof(int), stream_));
+    VD_TRY(launch_check_finite(dd, 3 * N, d_flags_, stream_));
+    VD_TRY(hipMemcpyAsync(h_flags_, d_flags_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    VD_CHECK(finest_energy(&e[0]));  // synchronises: h_flags_ is valid too
+    if (h_flags_[0]) return VD_EINVAL;
+    VD_TRY(hipMemcpyAsync(warm_d_, F.d, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+    VD_TRY(hipMemcpyAsync(warm_rot_, F.rot, 9 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+    VD_TRY(launch_add_delta<T>(F.d, dd, F.h, 3 * (int64_t)N, stream_));
+    const LevelView<T> V = F.view(desc_.w_arap);
+    VD_TRY(launch_polar<T>(nodes_of(V), stream_));
+    VD_CHECK(finest_energy(&e[1]));
+    *used = (e[1] <= e[0]) ? 1 : 0;
+    if (!*used) {
+      VD_TRY(hipMemcpyAsync(F.d, warm_d_, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
+      VD_TRY(hipMemcpyAsync(F.rot, warm_rot_, 9 * N * sizeof(T), hipMemcpyDeviceToDevice,
+                            stream_));
+    }
+    energy_fresh_ = false;
+    return VD_OK;
+  }
+
+  // One flip-flop iteration on the finest level followed by the energy.
+  int enqueue_gn_finest(hipStream_t s) {
+    const LevelView<T> V = finest().view(desc_.w_arap);
+    const int pcg = desc_.pcg_iters[L_ - 1];
+    VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s));
+    for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), s));
+    if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
+    VD_TRY(launch_polar<T>(nodes_of(V), s));
+    VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, s));
+    return VD_OK;
+  }
+
+  // Target mode: finest-level iterations until E <= target or `cap` of them.
+  int run_target(double target, int cap, int* done, int* reached) {
+    const LevelView<T> V = finest().view(desc_.w_arap);
+    VD_TRY(launch_reset_counters<T>(one_of(V), stream_));
+    double e = 0.0;
+    VD_CHECK(finest_energy(&e));
+    *done = 0;
+    *reached = e <= target ? 1 : 0;
+    const bool graph = (desc_.flags & VD_FLAG_GRAPH) != 0;
+    if (graph && (gn_graph_gen_ != alloc_gen_ || !gn_graph_)) {
+      if (gn_graph_) {
+        VD_TRY(hipGraphExecDestroy(gn_graph_));
+        gn_graph_ = nullptr;
+      }
+      if (!capture_stream_)
+        VD_TRY(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      VD_TRY(hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue_gn_finest(capture_stream_);
+      const hipError_t ec = hipStreamEndCapture(capture_stream_, &g);
+      if (rc != VD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess) return VD_EHIP;
+      const hipError_t ei = hipGraphInstantiate(&gn_graph_, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return VD_EHIP;
+      gn_graph_gen_ = alloc_gen_;
+    }
+    while (!*reached && *done < cap) {
+      if (graph) {
+        VD_TRY(hipGraphLaunch(gn_graph_, stream_));
+      } else {
+        VD_CHECK(enqueue_gn_finest(stream_));
+      }
+      VD_TRY(hipMemcpyAsync(h_sc_, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+      ++*done;
+      if (h_sc_->energy[0] <= target) *reached = 1;
+    }
+    return VD_OK;
+  }
+
   int ensure_partials(LevelData<T>& v, int cap_rows) {
     const int need = 3 * energy_blocks(cap_rows, v.N);
     if (need <= v.cap_pe) return VD_OK;
@@ -842,6 +1003,13 @@ class Solver final : public ISolver {
   // test scratch
   float* dbg_f_ = nullptr;
   T *dbg_t1_ = nullptr, *dbg_t2_ = nullptr, *dbg_rot_ = nullptr;
+  // warm start
+  T *warm_d_ = nullptr, *warm_rot_ = nullptr;  // plain initialisation kept for the judge
+  hipGraphExec_t gn_graph_ = nullptr;          // one finest-level iteration (target mode)
+  long gn_graph_gen_ = -1;
+  float* feat_scratch_ = nullptr;  // per-row residual pieces of the features
+  size_t feat_cap_ = 0;
+  uint16_t* feat_x_ = nullptr;     // features staged for a host copy
 };
 
 // ===========================================================================
@@ -892,6 +1060,7 @@ class Batch final : public IBatch {
   }
 
   int solve(const vd_solve_opts* o, double* energies) override {
+    if (o && (o->init_delta || o->energy_target != 0.0)) return VD_EINVAL;  // single-lattice only
     for (auto* h : h_)
       if (!h->has_constraints()) return VD_ESTATE;
     const int reset = (o && o->reset_to_rest) ? 1 : 0;
@@ -1209,6 +1378,11 @@ const char* vd_strerror(int code) {
 int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out) {
   if (!l) return VD_EINVAL;
   return l->impl->tune(iters, tile_out, us_out);
+}
+
+int vd_warm_features(vd_lattice* l, const float* prev2, uint16_t* x, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->warm_features(prev2, x, mem);
 }
 
 int vd_debug_apply(vd_lattice* l, int32_t level, const float* p, float* Ap, int32_t mem) {

@@ -518,6 +518,19 @@ hipError_t launch_state_io(const LevelView<T>& L, const double* o, float* pos, f
 
 // AoS float xyz <-> SoA T (used by the test entry points)
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_delta(T* d, const float* delta, T h, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) d[i] += h * (T)delta[i];
+}
+
+template <typename T>
+hipError_t launch_add_delta(T* d, const float* delta, double h, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_add_delta<T><<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(d, delta, (T)h, n);
+  return hipGetLastError();
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_convert(const float* in, T* out, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -557,6 +570,7 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \
                                          const float*, const float*, int, int*, hipStream_t);   \
   template hipError_t launch_convert<T>(const float*, T*, int, hipStream_t);                    \
+  template hipError_t launch_add_delta<T>(T*, const float*, double, int64_t, hipStream_t);      \
   template hipError_t launch_convert_back<T>(const T*, float*, int, hipStream_t);               \
   template hipError_t launch_fit_batch<T>(const float*, const float*, float*, int*, int64_t,    \
                                           hipStream_t);

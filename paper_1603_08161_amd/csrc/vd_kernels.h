@@ -209,6 +209,10 @@ hipError_t launch_state_io(const LevelView<T>& L, const double* origin, float* p
                            const float* pos_in, const float* rot_in, int dir, int* flags,
                            hipStream_t s);
 
+// d[i] += h * delta[i] for the 3N displacement entries (warm start).
+template <typename T>
+hipError_t launch_add_delta(T* d, const float* delta, double h, int64_t n, hipStream_t s);
+
 template <typename T>
 hipError_t launch_convert(const float* in, T* out, int n, hipStream_t s);
 template <typename T>

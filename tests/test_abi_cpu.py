@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI (no GPU needed): the library loads and
-exports every function include/vd.h declares, the ctypes structures have the
+exports every function include/vd.h and include/vd_net.h declare, the ctypes structures have the
 C layout (checked against a gcc-compiled probe of the header), and argument
 validation that happens before any device work."""
 
@@ -12,18 +12,20 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vd.h")
+HEADERS = [HEADER, os.path.join(ROOT, "include", "vd_net.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(vd_\w+)\s*\(", text, re.M)))
+    text = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(vd_\w+)\s*\(",
+                                 text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
     import paper_1603_08161_amd as vd
     lib = ctypes.CDLL(vd.LIB_PATH)
     names = _declared()
-    assert len(names) >= 16
+    assert len(names) >= 28
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(vd.EXPORTED) == names
@@ -46,7 +48,10 @@ int main(void) {
          offsetof(vd_constraints, mem));
   printf("rep %zu %zu %zu %zu\n", sizeof(vd_solve_report), offsetof(vd_solve_report, n_trace),
          offsetof(vd_solve_report, trace), offsetof(vd_solve_report, prof_n));
-  printf("opts %zu\n", sizeof(vd_solve_opts));
+  printf("opts %zu %zu %zu %zu\n", sizeof(vd_solve_opts), offsetof(vd_solve_opts, init_delta),
+         offsetof(vd_solve_opts, energy_target), offsetof(vd_solve_opts, max_gn));
+  printf("rep2 %zu %zu %zu\n", offsetof(vd_solve_report, init_energy),
+         offsetof(vd_solve_report, warm_used), offsetof(vd_solve_report, target_reached));
   return 0;
 }
 ''')
@@ -64,7 +69,10 @@ int main(void) {
     assert out["cons"] == [ctypes.sizeof(Cs), Cs.n_sparse.offset, Cs.mem.offset]
     R = L.SolveReport
     assert out["rep"] == [ctypes.sizeof(R), R.n_trace.offset, R.trace.offset, R.prof_n.offset]
-    assert out["opts"] == [ctypes.sizeof(L.SolveOpts)]
+    O = L.SolveOpts
+    assert out["opts"] == [ctypes.sizeof(O), O.init_delta.offset, O.energy_target.offset,
+                           O.max_gn.offset]
+    assert out["rep2"] == [R.init_energy.offset, R.warm_used.offset, R.target_reached.offset]
 
 
 def test_create_rejects_bad_descriptors_without_a_gpu():
@@ -111,3 +119,14 @@ def test_fit_rotations_argument_checks_without_a_gpu():
     assert lib.vd_debug_fit_rotations(None, None, None, None, -1, 0, 0, None) == vd.VD_EINVAL
     assert lib.vd_debug_fit_rotations(None, None, None, None, 0, 7, 0, None) == vd.VD_EINVAL
     assert lib.vd_debug_fit_rotations(None, None, None, None, 0, 0, 0, None) == vd.VD_OK
+
+
+def test_net_param_count_and_create_checks_without_a_gpu():
+    import paper_1603_08161_amd._lib as L
+    from oracle import net as onet
+    assert L.Net.param_count() == sum(co * ci * 27 + co for _, ci, co, _, _ in onet.LAYERS)
+    h = ctypes.c_void_p()
+    for dims in [(0, 4, 4), (4, -1, 4)]:
+        rc = L.lib().vd_net_create(dims[0], dims[1], dims[2], 1, None, ctypes.byref(h))
+        assert rc == L.VD_EINVAL
+    assert L.lib().vd_net_create(4, 4, 4, 0, None, ctypes.byref(h)) == L.VD_EINVAL
