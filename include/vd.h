@@ -67,6 +67,9 @@ extern "C" {
 #define VD_FLAG_TRACE 2u /* record E_total after every half-step */
 #define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events
                               (ignored when VD_FLAG_GRAPH is set) */
+#define VD_FLAG_NO_PERSIST 8u /* run every CG iteration as its own launch, also
+                                 on levels small enough for the persistent
+                                 one-launch CG loop (at most 128 tiles) */
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
@@ -75,6 +78,7 @@ extern "C" {
 #define VD_PROF_ROTATION 3  /* rotation fits */
 #define VD_PROF_ENERGY 4    /* energy evaluation */
 #define VD_PROF_TRANSFER 5  /* injection / prolongation */
+#define VD_PROF_CG_LOOP 6   /* a whole CG solve in one persistent launch */
 #define VD_PROF_KINDS 8
 
 /* ---- report bits -------------------------------------------------------- */
@@ -84,6 +88,10 @@ extern "C" {
                                      the previous rotation */
 #define VD_REPORT_WARM_REJECTED 8u /* the predicted initialisation had the
                                       higher energy and was dropped */
+#define VD_REPORT_BARRIER_TIMEOUT 16u /* a persistent CG loop's grid barrier
+                                         gave up waiting: the frame's result
+                                         is unreliable (rerun it with
+                                         VD_FLAG_NO_PERSIST) */
 
 #define VD_MAX_LEVELS 4
 #define VD_MAX_TRACE 512

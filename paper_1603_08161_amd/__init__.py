@@ -18,4 +18,5 @@ from ._lib import (  # noqa: F401
     strerror,
     VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE,
     VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP, VD_REPORT_WARM_REJECTED,
+    VD_REPORT_BARRIER_TIMEOUT,
 )

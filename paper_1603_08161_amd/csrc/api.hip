@@ -366,6 +366,7 @@ class Solver final : public ISolver {
         if (target && l != L_ - 1) continue;
         VD_TRY(hipMemcpy(h_sc_, lv_[l].sc, sizeof(Scalars), hipMemcpyDeviceToHost));
         if (h_sc_->guard_hits) rep->bits |= VD_REPORT_PCG_GUARD;
+        if (h_sc_->bar_timeouts) rep->bits |= VD_REPORT_BARRIER_TIMEOUT;
         rep->polar_fp64 += h_sc_->polar_fp64;
         rep->polar_keep += h_sc_->polar_keep;
         for (int k = 0; k < h_sc_->n_trace && rep->n_trace < VD_MAX_TRACE; ++k)
@@ -695,15 +696,22 @@ class Solver final : public ISolver {
         VD_CHECK(timed(on, VD_PROF_ROTATION, s, [&] { return launch_polar<T>(nodes_of(V), s); }));
       }
       const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
+      const bool loop = persistent(v);
       for (int k = 0; k < gn; ++k) {
         VD_CHECK(timed(on, VD_PROF_GRADIENT, s, [&] {
           return launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s);
         }));
-        for (int m = 0; m < pcg; ++m)
-          VD_CHECK(timed(on, VD_PROF_CG_A, s, [&] { return launch_cg<T>(m, tiles_of(V), s); }));
-        if (pcg > 0)
-          VD_CHECK(timed(on, VD_PROF_CG_B, s,
-                         [&] { return launch_cg_final<T>(pcg - 1, nodes_of(V), s); }));
+        if (loop && pcg > 0) {
+          VD_CHECK(timed(on, VD_PROF_CG_LOOP, s,
+                         [&] { return launch_cg_loop<T>(pcg, tiles_of(V), s); }));
+        } else {
+          for (int m = 0; m < pcg; ++m)
+            VD_CHECK(
+                timed(on, VD_PROF_CG_A, s, [&] { return launch_cg<T>(m, tiles_of(V), s); }));
+          if (pcg > 0)
+            VD_CHECK(timed(on, VD_PROF_CG_B, s,
+                           [&] { return launch_cg_final<T>(pcg - 1, nodes_of(V), s); }));
+        }
         if (trace) VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 1, s));
         VD_CHECK(timed(on, VD_PROF_ROTATION, s, [&] { return launch_polar<T>(nodes_of(V), s); }));
         if (trace) VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 1, s));
@@ -712,6 +720,12 @@ class Solver final : public ISolver {
     VD_CHECK(timed(prof, VD_PROF_ENERGY, s,
                    [&] { return launch_energy<T>(energy_of(FV), one_of(FV), 0, s); }));
     return VD_OK;
+  }
+
+  // Levels whose tiles all fit at once run each CG solve as one persistent
+  // launch (the per-iteration launches there are latency, not bandwidth).
+  bool persistent(const LevelData<T>& v) const {
+    return !(desc_.flags & VD_FLAG_NO_PERSIST) && v.ntiles <= kPersistMaxTiles;
   }
 
   template <typename F>
@@ -797,8 +811,12 @@ class Solver final : public ISolver {
     const LevelView<T> V = finest().view(desc_.w_arap);
     const int pcg = desc_.pcg_iters[L_ - 1];
     VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s));
-    for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), s));
-    if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
+    if (persistent(finest()) && pcg > 0) {
+      VD_TRY(launch_cg_loop<T>(pcg, tiles_of(V), s));
+    } else {
+      for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), s));
+      if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
+    }
     VD_TRY(launch_polar<T>(nodes_of(V), s));
     VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, s));
     return VD_OK;

@@ -186,6 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __re
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
   const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
+  // the CG solve that follows a gradient pass counts its grid barrier from 0
+  if (MODE == kModeRhs && w.local == 0 && threadIdx.x == 0) L.sc->bar = 0u;
   for (int k = threadIdx.x; k < TL::HALO; k += kBlock) {
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
@@ -309,11 +311,11 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& 
   if (count_guard && threadIdx.x == 0 && !(pap > 0.0)) sc->guard_hits += 1;
 }
 
+// One CG iteration m on the tile of workgroup w (body of k_cg and of the
+// persistent k_cg_loop).
 template <typename T, typename TL, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
-  __shared__ T sp[3][TL::HALO];
-  __shared__ T sr[3][TL::HALO];
-  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+__device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
+                                        T (&sr)[3][TL::HALO]) {
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
@@ -420,6 +422,79 @@ __global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
   write_partials<4>(part, s_out, w.count, w.local);
 }
 
+template <typename T, typename TL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
+  __shared__ T sp[3][TL::HALO];
+  __shared__ T sr[3][TL::HALO];
+  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+  cg_body<T, TL, FIRST>(w, m, sp, sr);
+}
+
+// Grid barrier of a launch whose workgroups are all resident: every
+// workgroup publishes its writes (agent-scope release), counts itself in,
+// waits for `target` arrivals and then acquires.  The wait is bounded: after
+// kSpinLimit polls it gives up and counts a timeout, so the kernel always
+// ends (the result of such a frame is then reported as unreliable).
+constexpr unsigned kSpinLimit = 1u << 18;
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* timeouts) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        atomicAdd(timeouts, 1);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// The last step d += alpha p of CG iterate `last` on the tile's own nodes.
+template <typename T, typename TL>
+__device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
+  const LevelView<T>& L = w.L;
+  const TilePos<TL> t(L.nx, L.ny, w.local);
+  const bool odd = (last & 1) != 0;
+  T alpha, beta;
+  cg_scalars<T>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  const size_t N = L.N;
+  const T* __restrict__ p = odd ? L.pb : L.pa;
+  T* __restrict__ d = L.d;
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a * N + i] += alpha * p[a * N + i];
+  }
+}
+
+// All iterations of one CG solve (single lattice, every tile resident).
+template <typename T, typename TL>
+__global__ __launch_bounds__(kBlock) void k_cg_loop(Dispatch<T> D, int iters) {
+  __shared__ T sp[3][TL::HALO];
+  __shared__ T sr[3][TL::HALO];
+  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+  Scalars* sc = w.L.sc;
+  for (int m = 0; m < iters; ++m) {
+    if (m == 0)
+      cg_body<T, TL, true>(w, m, sp, sr);
+    else
+      cg_body<T, TL, false>(w, m, sp, sr);
+    grid_barrier(&sc->bar, (unsigned)(m + 1) * gridDim.x, &sc->bar_timeouts);
+  }
+  cg_final_tile<T, TL>(w, iters - 1);
+}
+
 // d += alpha p of the last CG iterate (node workgroups).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
@@ -458,6 +533,19 @@ template <typename T>
 hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s) {
   if (D.blocks <= 0) return hipSuccess;
   k_cg_final<T><<<D.blocks, kBlock, 0, s>>>(D, last);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s) {
+  if (D.blocks <= 0 || iters <= 0) return hipSuccess;
+  if (D.n != 1 || D.blocks > kPersistMaxTiles || D.blocks != D.one.ntiles)
+    return hipErrorInvalidValue;
+  switch (D.one.tile) {
+    case 1: k_cg_loop<T, TileM><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
+    case 2: k_cg_loop<T, TileW><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
+    default: k_cg_loop<T, TileS><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
+  }
   return hipGetLastError();
 }
 
@@ -571,6 +659,7 @@ __global__ void k_reset_counters(Dispatch<T> D1) {
   sc->polar_fp64 = 0;
   sc->polar_keep = 0;
   sc->n_trace = 0;
+  sc->bar_timeouts = 0;
 }
 
 template <typename T>
@@ -744,6 +833,7 @@ hipError_t launch_set_rest(const Dispatch<T>& D, hipStream_t s) {
   template hipError_t launch_cg_final<T>(int, const Dispatch<T>&, hipStream_t);                  \
   template hipError_t launch_energy<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
   template hipError_t launch_reset_counters<T>(const Dispatch<T>&, hipStream_t);                 \
+  template hipError_t launch_cg_loop<T>(int, const Dispatch<T>&, hipStream_t);                   \
   template hipError_t launch_polar<T>(const Dispatch<T>&, hipStream_t);                          \
   template hipError_t launch_inject<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
   template hipError_t launch_prolong<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \

@@ -25,6 +25,8 @@ struct Scalars {
   int n_trace;
   int rows;        // constraint rows of the current frame (dense + 3 sparse)
   int n_dense;     // dense rows among them
+  unsigned bar;      // arrivals at the grid barrier of the persistent CG loop
+  int bar_timeouts;  // grid barrier waits that gave up (bounded spin)
   double trace[VD_MAX_TRACE];
 };
 
@@ -158,6 +160,13 @@ hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s);
 // d += alpha p of CG iterate `last` (node workgroups).
 template <typename T>
 hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s);
+
+// All `iters` CG iterations and the last step of one position solve in one
+// launch (one lattice; all its tiles resident at once, with a grid barrier
+// between iterations).  Same arithmetic as launch_cg + launch_cg_final.
+constexpr int kPersistMaxTiles = 128;
+template <typename T>
+hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s);
 
 // Energy of eq. (1) into each lattice's sc->energy (rows+nodes workgroups for
 // De, one workgroup per lattice for D1).

@@ -19,6 +19,7 @@ def _check_against_oracle(scene, lat_kw=None, e_tol=1e-4, x_tol=1e-3):
     ref = oracle.solve_frame(scene)
     lat = make_lattice(scene, **(lat_kw or {}))
     rep = lat.solve_frame(report=True)
+    assert not rep["bits"] & 16  # no grid-barrier timeout in a persistent CG loop
     pos, rot = lat.get_state()
     h = scene.spec.spacing
     dx = np.abs(pos.astype(np.float64) - ref["t"]).max() / h
@@ -194,3 +195,26 @@ def test_autotuner_keeps_parity():
     assert all(u > 0 for u in us[0])
     rep = lat.solve_frame(report=True)
     assert abs(rep["energy"][0] / ref["energy"][0] - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("maker,precision,graph", [(make_config0, "fp32", False),
+                                                   (make_config0, "fp64", True),
+                                                   (make_config1, "fp32", True)])
+def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, graph):
+    """Levels with at most 128 tiles run each CG solve as one persistent
+    launch with grid barriers; it computes the same iterates as one launch per
+    CG iteration (same operations, so equal up to floating-point contraction
+    choices) and never times out."""
+    from paper_1603_08161_amd import VD_REPORT_BARRIER_TIMEOUT
+    scene = maker(0)
+    out = {}
+    for persistent in (True, False):
+        lat = make_lattice(scene, precision=precision, graph=graph, persistent=persistent)
+        rep = lat.solve_frame(report=True)
+        assert not rep["bits"] & VD_REPORT_BARRIER_TIMEOUT
+        out[persistent] = (rep["energy"], lat.get_state()[0])
+    h = scene.spec.spacing
+    tol = 1e-6 if precision == "fp32" else 1e-12
+    assert abs(out[True][0][0] / out[False][0][0] - 1.0) < tol
+    dx = np.abs(out[True][1].astype(np.float64) - out[False][1]).max() / h
+    assert dx < (1e-5 if precision == "fp32" else 1e-6), dx
