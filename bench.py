@@ -41,6 +41,54 @@ def cg_iteration_bytes(n_nodes: int, n_dense: int, n_sparse: int, elem: int = 4)
     return 36.0 * elem * n_nodes + 24.0 * n_dense + 12.0 * n_sparse
 
 
+def kernel_source_sha() -> str:
+    """Hash of the sources the CG-iteration kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("solve.hip", "vd_device.h", "vd_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1603_08161_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str = "traffic_k_cg_frame64.md"):
+    """HBM bytes per launch of the 64^3 CG-iteration kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy), or None if the summary is missing or the
+    kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib: int = 1024, reps: int = 3) -> int:
+    """A plain device copy of known size, the calibration of the PMC byte
+    counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copy-probe: {reps} copies of {n * 4} bytes (read {n * 4}, write {n * 4} each)",
+          flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +100,11 @@ def main() -> int:
     ap.add_argument("--workload", choices=["frame64", "batch32"], default="frame64",
                     help="frame64: the 64^3 single-frame metric (default); batch32: 32 uneven "
                          "lattices solved together")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        return copy_probe()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is "
               "single-GPU and has no multi-GPU path.", file=sys.stderr)
@@ -182,7 +234,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "bytes_per_launch": nbytes,
             "mean_us": cg_a_us,
         },
