@@ -100,6 +100,8 @@ def main() -> int:
     ap.add_argument("--workload", choices=["frame64", "batch32"], default="frame64",
                     help="frame64: the 64^3 single-frame metric (default); batch32: 32 uneven "
                          "lattices solved together")
+    ap.add_argument("--persistent", action="store_true",
+                    help="one persistent launch per CG solve on levels of <= 128 tiles")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -136,7 +138,7 @@ def main() -> int:
     # tile autotuning (setup, outside the timed region): the library times
     # each stencil tile shape per level on these constraints and keeps the
     # fastest for the captured schedule
-    lat = Lattice.from_spec(spec, graph=True)
+    lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent)
     lat.set_constraints(*inputs)
     tiles, tile_us = lat.tune(iters=10)
     print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4]: "

@@ -67,9 +67,10 @@ extern "C" {
 #define VD_FLAG_TRACE 2u /* record E_total after every half-step */
 #define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events
                               (ignored when VD_FLAG_GRAPH is set) */
-#define VD_FLAG_NO_PERSIST 8u /* run every CG iteration as its own launch, also
-                                 on levels small enough for the persistent
-                                 one-launch CG loop (at most 128 tiles) */
+#define VD_FLAG_PERSIST 8u /* on levels of at most 128 tiles, run each CG
+                              solve as one persistent launch with a grid
+                              barrier between iterations (default: one launch
+                              per CG iteration) */
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
@@ -90,8 +91,8 @@ extern "C" {
                                       higher energy and was dropped */
 #define VD_REPORT_BARRIER_TIMEOUT 16u /* a persistent CG loop's grid barrier
                                          gave up waiting: the frame's result
-                                         is unreliable (rerun it with
-                                         VD_FLAG_NO_PERSIST) */
+                                         is unreliable (rerun it without
+                                         VD_FLAG_PERSIST) */
 
 #define VD_MAX_LEVELS 4
 #define VD_MAX_TRACE 512

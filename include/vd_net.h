@@ -29,10 +29,10 @@
  * Layouts:
  *   - Input features x: [batch][nz][ny][nx][8] bfloat16 bit patterns
  *     (uint16), node (a,b,c) at a + nx*(b + ny*c) as in vd.h.  Channels:
- *     0-2 displacement t - t_hat of the previous frame, 3-5 that of the frame
- *     before, 6 the weight-normalised point-to-plane residual splatted to the
- *     nodes, 7 validity (1 where a sample touches the node) -- all lengths in
- *     units of the finest spacing (see vd_warm_features).
+ *     0-2 displacement t - t_hat of the previous frame, 3-5 its change from
+ *     the frame before, 6 the weight-normalised point-to-plane residual
+ *     splatted to the nodes, 7 validity (1 where a sample touches the node)
+ *     -- all lengths in units of the finest spacing (see vd_warm_features).
  *   - Output and training target: [batch][3][N] float32 (x block, y block,
  *     z block per sample), the displacement change in units of the spacing.
  *   - Parameters: one float32 vector, layer by layer in the order above; per
@@ -93,8 +93,9 @@ int vd_net_train_step(vd_net* n, const uint16_t* x, const float* target, int32_t
 /* Input features of the lattice's finest level for the coming frame, from
  * the current state (taken as the previous frame's solution, t^{k-1}), the
  * displacement prev2 of the frame before ([3][N] x/y/z blocks, world units,
- * NULL = same as the current state) and the correspondences last given to
- * vd_set_constraints.  Channel 6 at node i is
+ * NULL: no change) and the correspondences last given to
+ * vd_set_constraints.  Channels 0-2 are d/h for the current displacement d,
+ * channels 3-5 (d - prev2)/h (0 when prev2 is NULL).  Channel 6 at node i is
  *   sum_c alpha_ci w_c r_c / sum_c alpha_ci w_c,   r_c = n_c . (S(p_hat_c) - p_c)
  * over the dense samples c whose cell has node i as a corner (alpha the
  * trilinear weights of Sec. 4, S the warp at the current state, w_c the

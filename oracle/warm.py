@@ -5,7 +5,9 @@ Part of the CPU oracle -- test infrastructure only.
 For the coming frame k, each node i of the finest lattice gets 8 channels,
 all lengths divided by the node spacing h:
   0-2  t_i^{k-1} - t_hat_i   (the previous frame's solved displacement)
-  3-5  t_i^{k-2} - t_hat_i   (the frame before)
+  3-5  t_i^{k-1} - t_i^{k-2}  (its change from the frame before: the same
+       information as that frame's displacement, encoded as a difference so
+       that a small motion survives rounding to bfloat16)
   6    sum_c alpha_ci w_c r_c / sum_c alpha_ci w_c, with the point-to-plane
        residual r_c = n_c . (S(p_hat_c) - p_c) of eq. (2) evaluated at the
        plain initialisation t^{k-1}, the trilinear weights alpha of Sec. 4 and
@@ -29,7 +31,7 @@ def features(grid: Grid, cons: Constraints, t_prev: np.ndarray, t_prev2=None) ->
     t_prev2 = t_prev if t_prev2 is None else np.asarray(t_prev2, np.float64).reshape(-1, 3)
     out = np.zeros((grid.n, 8))
     out[:, 0:3] = (t_prev - rest) / grid.h
-    out[:, 3:6] = (t_prev2 - rest) / grid.h
+    out[:, 3:6] = (t_prev - t_prev2) / grid.h
     ids, alpha = trilinear(grid, cons.canon)
     warped = np.einsum("ck,cka->ca", alpha, t_prev[ids])          # S(p_hat_c)
     res = np.einsum("ca,ca->c", cons.normal, warped - cons.target)  # eq. (2) residual

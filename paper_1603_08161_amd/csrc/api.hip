@@ -722,10 +722,10 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
-  // Levels whose tiles all fit at once run each CG solve as one persistent
-  // launch (the per-iteration launches there are latency, not bandwidth).
+  // With VD_FLAG_PERSIST, levels whose tiles all fit at once run each CG
+  // solve as one persistent launch.
   bool persistent(const LevelData<T>& v) const {
-    return !(desc_.flags & VD_FLAG_NO_PERSIST) && v.ntiles <= kPersistMaxTiles;
+    return (desc_.flags & VD_FLAG_PERSIST) && v.ntiles <= kPersistMaxTiles;
   }
 
   template <typename F>

@@ -461,8 +461,9 @@ __global__ __launch_bounds__(kBlock) void k_features(LevelView<T> L, RowView<T> 
   const double inv_h = 1.0 / (double)L.h;
   float ch[8];
   for (int c = 0; c < 3; ++c) {
-    ch[c] = (float)((double)L.d[(size_t)c * L.N + i] * inv_h);
-    ch[3 + c] = prev2 ? (float)((double)prev2[(size_t)c * L.N + i] * inv_h) : ch[c];
+    const double d1 = (double)L.d[(size_t)c * L.N + i];
+    ch[c] = (float)(d1 * inv_h);
+    ch[3 + c] = prev2 ? (float)((d1 - (double)prev2[(size_t)c * L.N + i]) * inv_h) : 0.f;
   }
   ch[6] = den > 0.0 ? (float)(num / den * inv_h) : 0.f;
   ch[7] = den > 0.0 ? 1.f : 0.f;

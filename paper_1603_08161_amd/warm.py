@@ -29,11 +29,18 @@ from ._lib import Lattice, Net
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warm64.npz")
 
 
-def _sequence_scenes(args):
-    """Worker: all frames of one seeded sequence (host-only numpy work)."""
-    seed, frames, n = args
+def _frame_scene(args):
+    """Worker: one frame of one seeded sequence (host-only numpy work)."""
+    seed, k, n = args
     from synth.scenes import make_sequence_frame
-    return seed, [make_sequence_frame(seed, k, n=n) for k in range(frames)]
+    return make_sequence_frame(seed, k, n=n)
+
+
+def _one_thread():
+    """Worker initialiser: one BLAS/OpenMP thread per worker process, so the
+    pool does not oversubscribe the host cores."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
 
 
 def make_pool(workers: int):
@@ -42,18 +49,16 @@ def make_pool(workers: int):
     started by fork + exec."""
     if workers <= 0:
         return None
-    return mp.get_context("spawn").Pool(workers)
+    return mp.get_context("spawn").Pool(workers, initializer=_one_thread)
 
 
 def sequence_pool(pool, seeds, frames, n):
-    """Iterator over (seed, scenes) in seed order."""
-    jobs = [(s, frames, n) for s in seeds]
-    if pool is None:
-        for j in jobs:
-            yield _sequence_scenes(j)
-        return
-    for item in pool.imap(_sequence_scenes, jobs):
-        yield item
+    """Iterator over (seed, scenes) in seed order; the frames are generated in
+    parallel across the pool's workers."""
+    jobs = [(s, k, n) for s in seeds for k in range(frames)]
+    it = map(_frame_scene, jobs) if pool is None else pool.imap(_frame_scene, jobs)
+    for s in seeds:
+        yield s, [next(it) for _ in range(frames)]
 
 
 class SequenceRunner:
@@ -211,7 +216,14 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
         if runner is None:
             runner = SequenceRunner(scenes[0])
             out = torch.empty(3 * runner.n, dtype=torch.float32, device=device)
+            cv = torch.empty(3 * runner.n, dtype=torch.float32, device=device)
             xbuf = torch.empty(8 * runner.n, dtype=torch.int16, device=device)
+            rest_t = torch.from_numpy(runner.rest.T.astype(np.float32).copy()).to(device)
+
+            def lab_dev(pos, d_last=None):
+                """Solved displacement change (pos - t^{k-1}) / h as [3N]."""
+                dp = torch.from_numpy(pos.T.astype(np.float32).copy()).to(device) - rest_t
+                return ((dp - torch.from_numpy(d_prev).to(device)) / runner.h).reshape(-1)
         lat = runner.lat
         lat.set_scene(scenes[0])
         lat.solve_frame(reset=True)
@@ -246,13 +258,25 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
             t = time.perf_counter()
             rp = lat.solve_frame(report=True, energy_target=target, max_gn=max_gn)
             t_pt = time.perf_counter() - t
+            # (c) non-learned baseline: constant-velocity extrapolation of the
+            # last two frames, judged the same way
+            lat.set_state(pos0, rot0)
+            cv.copy_(torch.from_numpy(((d_prev - d_prev2) / runner.h).reshape(-1)))
+            rc = lat.solve_frame(report=True, init_delta=cv, energy_target=target,
+                                 max_gn=max_gn)
+            net_err = float(((out - lab_dev(pos1)) ** 2).sum() / runner.n)
             recs.append(dict(seed=seed, frame=k, e_plain=e_plain, t_plain_ms=1e3 * t_plain,
                              e_init_plain=rw["init_energy"][0],
                              e_init_warm=rw["init_energy"][1], warm_used=rw["warm_used"],
                              gn_warm=rw["gn_done"], reached_warm=rw["target_reached"],
                              e_warm=float(rw["energy"][0]), t_warm_ms=1e3 * t_warm,
                              gn_plain_target=rp["gn_done"], reached_plain=rp["target_reached"],
-                             t_plain_target_ms=1e3 * t_pt))
+                             t_plain_target_ms=1e3 * t_pt,
+                             e_init_cv=rc["init_energy"][1], cv_used=rc["warm_used"],
+                             gn_cv=rc["gn_done"], reached_cv=rc["target_reached"],
+                             pred_mse=net_err,
+                             cv_mse=float(((cv - lab_dev(pos1)) ** 2).sum() / runner.n),
+                             zero_mse=float((lab_dev(pos1) ** 2).sum() / runner.n)))
             # continue the chain with the plain solution
             lat.set_state(pos1, rot1)
             d = runner.disp()
@@ -260,7 +284,9 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
         r = recs[-1]
         log(f"# eval: sequence {seed}: last frame E_plain {r['e_plain']:.4f}, "
             f"init warm/plain {r['e_init_warm'] / r['e_init_plain']:.3f}, "
-            f"GN warm {r['gn_warm']} vs plain-init {r['gn_plain_target']}")
+            f"cv/plain {r['e_init_cv'] / r['e_init_plain']:.3f}, "
+            f"GN warm {r['gn_warm']} cv {r['gn_cv']} plain-init {r['gn_plain_target']}, "
+            f"mse net {r['pred_mse']:.2e} cv {r['cv_mse']:.2e} zero {r['zero_mse']:.2e}")
     return dict(frames=recs, summary=summarise(recs))
 
 
@@ -277,6 +303,12 @@ def summarise(recs: List[Dict]) -> Dict:
         t_plain_ms_mean=float(np.mean(a("t_plain_ms"))),
         t_warm_ms_mean=float(np.mean(a("t_warm_ms"))),
         t_plain_init_target_ms_mean=float(np.mean(a("t_plain_target_ms"))),
+        cv_init_energy_ratio_mean=float(np.mean(a("e_init_cv") / a("e_init_plain"))),
+        cv_reached_frac=float(np.mean(a("reached_cv"))),
+        gn_cv_mean=float(np.mean(a("gn_cv"))),
+        pred_mse_mean=float(np.mean(a("pred_mse"))),
+        cv_mse_mean=float(np.mean(a("cv_mse"))),
+        zero_mse_mean=float(np.mean(a("zero_mse"))),
         speedup_vs_plain_schedule=float(np.mean(a("t_plain_ms")) / np.mean(a("t_warm_ms"))),
     )
 

@@ -168,8 +168,8 @@ def test_features_match_oracle():
                           pos2.astype(np.float64))
     got = _from_bits(x.reshape(-1, 8))
     rb = onet.bf16_round(ref)
-    # displacements: the kernels round float32 (pos - rest) / h once
-    np.testing.assert_allclose(got[:, :6], rb[:, :6], rtol=2 ** -7, atol=1e-6)
+    # displacements and their change: float32 differences rounded once
+    np.testing.assert_allclose(got[:, :6], rb[:, :6], rtol=2 ** -7, atol=1e-5)
     assert np.array_equal(got[:, 7], ref[:, 7])
     assert ref[:, 7].sum() > 100
     scale = np.abs(ref[:, 6]).max()

@@ -201,10 +201,10 @@ def test_autotuner_keeps_parity():
                                                    (make_config0, "fp64", True),
                                                    (make_config1, "fp32", True)])
 def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, graph):
-    """Levels with at most 128 tiles run each CG solve as one persistent
-    launch with grid barriers; it computes the same iterates as one launch per
-    CG iteration (same operations, so equal up to floating-point contraction
-    choices) and never times out."""
+    """With VD_FLAG_PERSIST, levels with at most 128 tiles run each CG solve as
+    one persistent launch with grid barriers; it computes the same iterates as
+    one launch per CG iteration (same operations, so equal up to
+    floating-point contraction choices) and never times out."""
     from paper_1603_08161_amd import VD_REPORT_BARRIER_TIMEOUT
     scene = maker(0)
     out = {}
