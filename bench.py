@@ -100,6 +100,10 @@ def main() -> int:
     ap.add_argument("--workload", choices=["frame64", "batch32"], default="frame64",
                     help="frame64: the 64^3 single-frame metric (default); batch32: 32 uneven "
                          "lattices solved together")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the warm-vs-plain leg (held-out sequence, committed weights)")
+    ap.add_argument("--warm-frames", type=int, default=10,
+                    help="frames of the held-out sequence in the warm-vs-plain leg")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent launch per CG solve on levels of <= 128 tiles")
     ap.add_argument("--copy-probe", action="store_true",
@@ -191,6 +195,10 @@ def main() -> int:
                              f"FP64, single-threaded BLAS): {t_cpu:.2f} s"}
         print(f"# oracle: {t_cpu:.2f} s/frame, E = {e_ref:.9g}", flush=True)
 
+    warm_leg = None
+    if not args.no_warm:
+        warm_leg = warm_vs_plain(args.warm_frames)
+
     if e_ref is not None:
         rel = np.abs(energies[:, 0] / e_ref - 1.0)
         solved = int(np.sum(rel <= 1e-4))
@@ -242,9 +250,32 @@ def main() -> int:
         },
         "kernel_mean_us": prof_us,
         "cpu_baseline": out_cpu,
+        "warm_vs_plain": warm_leg,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def warm_vs_plain(frames: int):
+    """The learned warm start against the plain solve on a held-out 64^3
+    sequence (seed 1000, frames 2..frames-1), with the committed weights: per
+    frame the plain schedule's time and energy, then the time and finest-level
+    iterations to reach that energy from the judged prediction and from the
+    plain initialisation (see paper_1603_08161_amd/warm.py)."""
+    import torch
+
+    from paper_1603_08161_amd import Net, warm
+    if not os.path.exists(warm.WEIGHTS):
+        print(f"# warm-vs-plain skipped: {warm.WEIGHTS} missing", flush=True)
+        return None
+    net = Net((64, 64, 64))
+    net.set_params(warm.load_weights())
+    res = warm.evaluate(net, None, [1000], frames, 64, torch.device("cuda", 0),
+                        log=lambda m: print(m, flush=True))
+    out = dict(res["summary"])
+    out["sequence"] = "held-out seed 1000, 64^3, frames 2.." + str(frames - 1)
+    out["stopping_rule"] = "finest-level flip-flop iterations until E <= plain schedule's E"
+    return out
 
 
 def bench_batch(args) -> int:
