@@ -65,8 +65,10 @@ extern "C" {
 #define VD_FLAG_GRAPH 1u /* capture each frame's schedule in a hipGraph and
                             replay it (default launch path when set) */
 #define VD_FLAG_TRACE 2u /* record E_total after every half-step */
-#define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events
-                              (ignored when VD_FLAG_GRAPH is set) */
+#define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events;
+                              with VD_FLAG_GRAPH, events inside the captured
+                              frame time the finest level's CG iterations
+                              (class VD_PROF_CG_A) of every replay */
 #define VD_FLAG_PERSIST 8u /* on levels of at most 128 tiles, run each CG
                               solve as one persistent launch with a grid
                               barrier between iterations (default: one launch
@@ -238,6 +240,11 @@ int vd_batch_profile(vd_batch* b, double prof_us[VD_PROF_KINDS], int32_t prof_n[
 
 /* Free the batch (not the handles).  NULL is a no-op. */
 int vd_batch_destroy(vd_batch* b);
+
+/* Mean duration (us) and count of the launches per kernel class (VD_PROF_*)
+ * timed during the last frame (VD_FLAG_PROFILE; zeros otherwise).  Waits for
+ * the stream. */
+int vd_get_profile(vd_lattice* l, double prof_us[VD_PROF_KINDS], int32_t prof_n[VD_PROF_KINDS]);
 
 /* Energy terms at the current finest state, eq. (1): out = {E_total,
  * w_d E_dense, w_s E_sparse, w_r E_reg}.  Waits for the stream. */

@@ -43,7 +43,7 @@ EXPORTED = (
     "vd_debug_apply", "vd_debug_gradient", "vd_debug_energy", "vd_debug_diag",
     "vd_debug_rotations", "vd_debug_fit_rotations", "vd_debug_prolong", "vd_tune",
     "vd_batch_create", "vd_batch_solve", "vd_batch_destroy", "vd_batch_profile",
-    "vd_warm_features", "vd_net_param_count", "vd_net_create", "vd_net_destroy",
+    "vd_get_profile", "vd_warm_features", "vd_net_param_count", "vd_net_create", "vd_net_destroy",
     "vd_net_set_params", "vd_net_get_params", "vd_net_forward", "vd_net_gradients",
     "vd_net_train_step",
 )
@@ -144,6 +144,7 @@ def _load() -> C.CDLL:
         "vd_batch_solve": ([vp, C.POINTER(SolveOpts), dp], C.c_int),
         "vd_batch_destroy": ([vp], C.c_int),
         "vd_batch_profile": ([vp, dp, C.POINTER(C.c_int32)], C.c_int),
+        "vd_get_profile": ([vp, dp, C.POINTER(C.c_int32)], C.c_int),
         "vd_warm_features": ([vp, vp, vp, i32], C.c_int),
         "vd_net_param_count": ([], i64),
         "vd_net_create": ([i32, i32, i32, i32, vp, C.POINTER(vp)], C.c_int),
@@ -356,6 +357,14 @@ class Lattice:
         _check(_lib.vd_warm_features(self._h, p2, x.ctypes.data, VD_MEM_HOST), "vd_warm_features")
         del keep
         return x.reshape(self.level_info(self.num_levels - 1)[0][::-1] + (8,))
+
+    def profile(self):
+        """Mean us per launch by kernel class over the last frame (profile=True)."""
+        us = (C.c_double * VD_PROF_KINDS)()
+        n = (C.c_int32 * VD_PROF_KINDS)()
+        _check(_lib.vd_get_profile(self._h, us, n), "vd_get_profile")
+        return ({PROF_NAMES[k]: float(us[k]) for k in range(len(PROF_NAMES)) if n[k] > 0},
+                {PROF_NAMES[k]: int(n[k]) for k in range(len(PROF_NAMES)) if n[k] > 0})
 
     def tune(self, iters: int = 10):
         """Run the library's tile autotuner; returns (tiles per level, mean us per

@@ -76,9 +76,10 @@ class EventTimer {
     used_ = 0;
   }
   // Runs `launch` (returning hipError_t); when `on`, brackets it with a pair
-  // of events attributed to kernel class `kind`.
+  // of events attributed to kernel class `kind`; `count` is the number of
+  // launches of that class between the two events (their mean is reported).
   template <typename F>
-  int timed(bool on, int kind, hipStream_t s, F&& launch) {
+  int timed(bool on, int kind, hipStream_t s, F&& launch, int count = 1) {
     if (!on) return launch() == hipSuccess ? VD_OK : VD_EHIP;
     while (pool_.size() < used_ + 2) {
       hipEvent_t e;
@@ -90,7 +91,7 @@ class EventTimer {
     if (hipEventRecord(pool_[a], s) != hipSuccess) return VD_EHIP;
     if (launch() != hipSuccess) return VD_EHIP;
     if (hipEventRecord(pool_[b], s) != hipSuccess) return VD_EHIP;
-    recs_.push_back(Rec{kind, a, b});
+    recs_.push_back(Rec{kind, a, b, count});
     return VD_OK;
   }
   // Mean microseconds and launch counts per kind (after the stream drained).
@@ -101,7 +102,7 @@ class EventTimer {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, pool_[r.a], pool_[r.b]) != hipSuccess) return VD_EHIP;
       sum[r.kind] += 1000.0 * ms;
-      n[r.kind] += 1;
+      n[r.kind] += r.count;
     }
     for (int k = 0; k < VD_PROF_KINDS; ++k) us[k] = n[k] ? sum[k] / n[k] : 0.0;
     return VD_OK;
@@ -109,7 +110,7 @@ class EventTimer {
 
  private:
   struct Rec {
-    int kind, a, b;
+    int kind, a, b, count;
   };
   std::vector<hipEvent_t> pool_;
   size_t used_ = 0;
@@ -198,6 +199,7 @@ class ISolver {
   virtual int debug_prolong(int level, const float* coarse, float* out, int mem) = 0;
   virtual int tune(int iters, int* tile_out, double* us_out) = 0;
   virtual int warm_features(const float* prev2, uint16_t* x, int mem) = 0;
+  virtual int profile(double* us, int* n) = 0;
 };
 
 template <typename T>
@@ -387,6 +389,12 @@ class Solver final : public ISolver {
       for (int k = 0; k < VD_PROF_KINDS; ++k) rep->prof_n[k] = pn[k];
     }
     return VD_OK;
+  }
+
+  // Mean durations of the timed launch classes of the last frame.
+  int profile(double* us, int* n) override {
+    VD_TRY(hipStreamSynchronize(stream_));
+    return timer_.collect(us, n);
   }
 
   // Features of vd_net.h for the coming frame (see vd_warm_features).
@@ -679,7 +687,8 @@ class Solver final : public ISolver {
   int enqueue_frame(int reset, hipStream_t s) {
     const double wr = desc_.w_arap;
     const bool trace = (desc_.flags & VD_FLAG_TRACE) != 0;
-    const bool prof = (desc_.flags & VD_FLAG_PROFILE) && !(desc_.flags & VD_FLAG_GRAPH);
+    const bool graph_prof = (desc_.flags & VD_FLAG_PROFILE) && (desc_.flags & VD_FLAG_GRAPH);
+    const bool prof = (desc_.flags & VD_FLAG_PROFILE) && !graph_prof;
     timer_.reset();
     const LevelView<T> FV = finest().view(wr);
     if (reset) VD_TRY(launch_set_rest<T>(nodes_of(FV), s));
@@ -704,6 +713,21 @@ class Solver final : public ISolver {
         if (loop && pcg > 0) {
           VD_CHECK(timed(on, VD_PROF_CG_LOOP, s,
                          [&] { return launch_cg_loop<T>(pcg, tiles_of(V), s); }));
+        } else if (graph_prof && l == L_ - 1 && pcg > 1) {
+          // captured frame: one event pair around the iterations after the
+          // first (the kernel of the roofline), replayed with the graph
+          VD_TRY(launch_cg<T>(0, tiles_of(V), s));
+          VD_CHECK(timed(
+              true, VD_PROF_CG_A, s,
+              [&] {
+                for (int m = 1; m < pcg; ++m) {
+                  const hipError_t e = launch_cg<T>(m, tiles_of(V), s);
+                  if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+              },
+              pcg - 1));
+          VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
         } else {
           for (int m = 0; m < pcg; ++m)
             VD_CHECK(
@@ -729,8 +753,8 @@ class Solver final : public ISolver {
   }
 
   template <typename F>
-  int timed(bool on, int kind, hipStream_t s, F&& launch) {
-    return timer_.timed(on, kind, s, launch);
+  int timed(bool on, int kind, hipStream_t s, F&& launch, int count = 1) {
+    return timer_.timed(on, kind, s, launch, count);
   }
 
   int run_graph(int reset) {
@@ -1396,6 +1420,11 @@ const char* vd_strerror(int code) {
 int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out) {
   if (!l) return VD_EINVAL;
   return l->impl->tune(iters, tile_out, us_out);
+}
+
+int vd_get_profile(vd_lattice* l, double* prof_us, int32_t* prof_n) {
+  if (!l || !prof_us || !prof_n) return VD_EINVAL;
+  return l->impl->profile(prof_us, prof_n);
 }
 
 int vd_warm_features(vd_lattice* l, const float* prev2, uint16_t* x, int32_t mem) {

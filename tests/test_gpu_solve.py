@@ -218,3 +218,20 @@ def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, gra
     assert abs(out[True][0][0] / out[False][0][0] - 1.0) < tol
     dx = np.abs(out[True][1].astype(np.float64) - out[False][1]).max() / h
     assert dx < (1e-5 if precision == "fp32" else 1e-6), dx
+
+
+def test_graph_profile_events_time_the_finest_cg_and_change_nothing():
+    """With graph + profile, HIP events captured in the frame time the finest
+    level's CG iterations of every replay; the solve itself is unchanged."""
+    scene = make_config1(0)
+    plain = make_lattice(scene, graph=True)
+    plain.solve_frame()
+    e_plain = plain.get_energy()
+    prof = make_lattice(scene, graph=True, profile=True)
+    for _ in range(2):
+        prof.solve_frame(reset=True)
+    us, n = prof.profile()
+    gn, pcg = scene.spec.gn_iters[-1], scene.spec.pcg_iters[-1]
+    assert n["cg_a"] == gn * (pcg - 1)
+    assert 0.5 < us["cg_a"] < 5000.0
+    np.testing.assert_array_equal(prof.get_energy(), e_plain)
