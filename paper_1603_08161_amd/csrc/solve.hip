@@ -127,9 +127,12 @@ struct TilePos {
 // (all 27 stencil neighbours of a tile node are in it; nodes outside the
 // lattice hold 0 and have zero blocks).
 
+// A p at own node c (tile-local) / i (global) from the tile's p in LDS:
+// the ARAP Laplacian plus the node's 27-point data blocks at A27 slot `slot`
+// (-1: no data term touches the node).
 template <typename T, typename TL>
 __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
-                                         int gx, int gy, int gz, size_t i, T& o0, T& o1,
+                                         int gx, int gy, int gz, int slot, T& o0, T& o1,
                                          T& o2) {
   const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
   T l0 = T(0), l1 = T(0), l2 = T(0);
@@ -155,7 +158,6 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
   o0 = w2 * l0;
   o1 = w2 * l1;
   o2 = w2 * l2;
-  const int slot = L.node_slot[i];
   if (slot >= 0) {
     const size_t cap = L.capA;
     const T* __restrict__ A = L.A27 + slot;
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __re
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o0, o1, o2;
-    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o0, o1, o2);
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, L.node_slot[i], o0, o1, o2);
     if (MODE == kModeApply) {
       out[i] = o0;
       out[N + i] = o1;
@@ -360,6 +362,25 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       }
     }
   }
+  // own nodes' data-block slot and preconditioner, loaded with the halo so
+  // they are off the dependent chain of step 4
+  int own_slot[TL::NPT];
+  T own_q[TL::NPT][3];
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    own_slot[kk] = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) own_q[kk][a] = T(0);
+    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+      const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+      own_slot[kk] = L.node_slot[i];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) own_q[kk][a] = dinv[a * N + i];
+    }
+  }
   // 2. CG scalars of the previous iterate
   T alpha = T(0), beta = T(0);
   if (!FIRST) cg_scalars<T>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
@@ -406,12 +427,12 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
-    apply_at<T, TL>(L, sp, c, gx, gy, gz, i, o[0], o[1], o[2]);
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, own_slot[kk], o[0], o[1], o[2]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const size_t j = a * N + i;
       ap_out[j] = o[a];
-      const double q = (double)dinv[j], r = (double)sr[a][c], p = (double)sp[a][c];
+      const double q = (double)own_q[kk][a], r = (double)sr[a][c], p = (double)sp[a][c];
       const double ap = (double)o[a];
       part[0] += r * q * r;
       part[1] += p * ap;
