@@ -66,9 +66,10 @@ extern "C" {
                             replay it (default launch path when set) */
 #define VD_FLAG_TRACE 2u /* record E_total after every half-step */
 #define VD_FLAG_PROFILE 4u /* time every finest-level launch with HIP events;
-                              with VD_FLAG_GRAPH, events inside the captured
-                              frame time the finest level's CG iterations
-                              (class VD_PROF_CG_A) of every replay */
+                              with VD_FLAG_GRAPH, device clock stamps captured
+                              in the frame time the finest level's CG
+                              iterations (class VD_PROF_CG_A) of every
+                              replay */
 #define VD_FLAG_PERSIST 8u /* on levels of at most 128 tiles, run each CG
                               solve as one persistent launch with a grid
                               barrier between iterations (default: one launch

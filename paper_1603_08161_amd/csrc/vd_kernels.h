@@ -207,6 +207,10 @@ inline Dispatch<T> single(const LevelView<T>& L, int blocks) {
   return D;
 }
 
+// dst[idx] = the device's constant-rate wall clock (one thread), for timing
+// launches inside a captured graph.
+hipError_t launch_stamp(unsigned long long* dst, int idx, hipStream_t s);
+
 // flags |= 1 where any of the n floats is not finite.
 hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s);
 
