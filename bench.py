@@ -11,8 +11,9 @@ Also reported:
 * roofline -- the fused CG-iteration kernel on the 64^3 level (one launch =
   one Jacobi-PCG iteration): algorithmic bytes per iteration (144 B per node
   + 24 B per dense and 12 B per sparse sample, float32) over its mean
-  duration, timed by HIP events that the library captures into the frame's
-  graph around those launches (read back after the timed replays);
+  duration, timed by device clock stamps that the library captures into the
+  frame's graph around those launches (read back after the timed replays);
+  traffic from the committed rocprofv3 byte-counter summary;
 * cpu_baseline -- the FP64 oracle timed on this host on one full frame.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -165,9 +166,9 @@ def main() -> int:
     energies = np.array(energies)
     print(f"# timed {args.steps} frames in {elapsed * 1e3:.2f} ms", flush=True)
 
-    # roofline of the dominant kernel: HIP events captured in the frame's
-    # graph around the 64^3 level's CG iterations, read back from the last
-    # timed replay (the same stream and launches as the timed region)
+    # roofline of the dominant kernel: device clock stamps captured in the
+    # frame's graph around the 64^3 level's CG iterations, read back from the
+    # last timed replay (the same stream and launches as the timed region)
     graph_us, graph_n = lat.profile()
     cg_a_us = float(graph_us["cg_a"])
     # the other kernel classes: a profiled eager replay of the same frame
@@ -249,8 +250,9 @@ def main() -> int:
             "traffic": measured_traffic(),
             "bytes_per_launch": nbytes,
             "mean_us": cg_a_us,
-            "timing": "HIP events in the captured frame around the 64^3 level's CG "
-                      "iterations 1..19 of each flip-flop iteration, last timed replay",
+            "timing": "device clock stamps captured in the frame graph around the 64^3 "
+                      "level's CG iterations 1..19 of each flip-flop iteration, last timed "
+                      "replay (rocprofv3 kernel-trace mean in profiles/k_cg_frame64.md)",
         },
         "kernel_mean_us_eager": prof_us,
         "cpu_baseline": out_cpu,
