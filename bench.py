@@ -103,7 +103,7 @@ def main() -> int:
                          "lattices solved together")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-plain leg (held-out sequence, committed weights)")
-    ap.add_argument("--warm-frames", type=int, default=10,
+    ap.add_argument("--warm-frames", type=int, default=22,
                     help="frames of the held-out sequence in the warm-vs-plain leg")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent launch per CG solve on levels of <= 128 tiles")
@@ -112,6 +112,12 @@ def main() -> int:
     args = ap.parse_args()
     if args.copy_probe:
         return copy_probe()
+    # the warm-vs-plain leg generates its held-out frames in worker processes,
+    # started before this process first touches the GPU
+    pool = None
+    if args.workload == "frame64" and not args.no_warm:
+        from paper_1603_08161_amd import warm
+        pool = warm.make_pool(min(8, os.cpu_count() or 1))
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is "
               "single-GPU and has no multi-GPU path.", file=sys.stderr)
@@ -200,7 +206,9 @@ def main() -> int:
 
     warm_leg = None
     if not args.no_warm:
-        warm_leg = warm_vs_plain(args.warm_frames)
+        warm_leg = warm_vs_plain(args.warm_frames, pool)
+        pool.close()
+        pool.join()
 
     if e_ref is not None:
         rel = np.abs(energies[:, 0] / e_ref - 1.0)
@@ -262,7 +270,7 @@ def main() -> int:
     return 0
 
 
-def warm_vs_plain(frames: int):
+def warm_vs_plain(frames: int, pool=None):
     """The learned warm start against the plain solve on a held-out 64^3
     sequence (seed 1000, frames 2..frames-1), with the committed weights: per
     frame the plain schedule's time and energy, then the time and finest-level
@@ -276,7 +284,7 @@ def warm_vs_plain(frames: int):
         return None
     net = Net((64, 64, 64))
     net.set_params(warm.load_weights())
-    res = warm.evaluate(net, None, [1000], frames, 64, torch.device("cuda", 0),
+    res = warm.evaluate(net, pool, [1000], frames, 64, torch.device("cuda", 0),
                         log=lambda m: print(m, flush=True))
     out = dict(res["summary"])
     out["sequence"] = "held-out seed 1000, 64^3, frames 2.." + str(frames - 1)

@@ -362,10 +362,12 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       }
     }
   }
-  // own nodes' data-block slot and preconditioner, loaded with the halo so
-  // they are off the dependent chain of step 4
+  // own nodes' data-block slot, preconditioner and displacement, loaded with
+  // the halo so they are off the dependent chain of steps 3 and 4
   int own_slot[TL::NPT];
   T own_q[TL::NPT][3];
+  T own_d[TL::NPT][3];
+  T own_pp[TL::NPT][3];  // p of the previous iterate (the step d += alpha p)
 #pragma unroll
   for (int kk = 0; kk < TL::NPT; ++kk) {
     const int c = TilePos<TL>::own(kk);
@@ -373,12 +375,22 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     own_slot[kk] = -1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) own_q[kk][a] = T(0);
+    for (int a = 0; a < 3; ++a) {
+      own_q[kk][a] = T(0);
+      own_d[kk][a] = T(0);
+      own_pp[kk][a] = T(0);
+    }
     if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) own_q[kk][a] = dinv[a * N + i];
+      for (int a = 0; a < 3; ++a) {
+        own_q[kk][a] = dinv[a * N + i];
+        if (!FIRST) {
+          own_d[kk][a] = L.d[a * N + i];
+          own_pp[kk][a] = p_in[a * N + i];
+        }
+      }
     }
   }
   // 2. CG scalars of the previous iterate
@@ -404,15 +416,11 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     if (hin[h] && lx >= 1 && lx <= TL::TX && ly >= 1 && ly <= TL::TY && lz >= 1 &&
         lz <= TL::TZ) {
-      T* __restrict__ d = L.d;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const size_t j = a * N + hi[h];
         p_out[j] = p3[a];
-        if (!FIRST) {
-          r_out[j] = r3[a];
-          d[j] += alpha * hp[h][a];
-        }
+        if (!FIRST) r_out[j] = r3[a];
       }
     }
   }
@@ -432,6 +440,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     for (int a = 0; a < 3; ++a) {
       const size_t j = a * N + i;
       ap_out[j] = o[a];
+      if (!FIRST) L.d[j] = own_d[kk][a] + alpha * own_pp[kk][a];
       const double q = (double)own_q[kk][a], r = (double)sr[a][c], p = (double)sp[a][c];
       const double ap = (double)o[a];
       part[0] += r * q * r;
