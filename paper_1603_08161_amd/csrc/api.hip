@@ -125,7 +125,7 @@ struct LevelData {
     *ap2 = nullptr, *dinv = nullptr, *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
   int* node_slot = nullptr;  // node -> row of A27 (-1: no data term)
-  T* A27 = nullptr;          // [27*6][N] data blocks of A, per node slot
+  T* A27 = nullptr;          // [N][kA27Row] data blocks of A, per node slot
   Scalars* sc = nullptr;
   double* scg[2] = {nullptr, nullptr};  // CG block partials [4][max_tiles], alternating
   double* pe = nullptr;                 // energy block partials [3][energy blocks]
@@ -253,7 +253,7 @@ class Solver final : public ISolver {
       VD_CHECK(pool_.alloc(&v.rot, 9 * N));
       VD_CHECK(pool_.alloc(&v.cell_map, (size_t)v.ncell));
       VD_CHECK(pool_.alloc(&v.node_slot, N));
-      VD_CHECK(pool_.alloc(&v.A27, 162 * N));
+      VD_CHECK(pool_.alloc(&v.A27, (size_t)kA27Row * N));
       VD_CHECK(pool_.alloc(&v.sc, 1));
       VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
       VD_CHECK(pool_.alloc(&v.r2, 3 * N));

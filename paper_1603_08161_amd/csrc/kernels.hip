@@ -333,8 +333,8 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
 
 // Per node: the data part of row i of A as a 27-point block stencil,
 // A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
-// = corner b, delta = b - a) of K_c[a][b]; stored SoA [27*6][capA] at the
-// node's compact slot.  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
+// = corner b, delta = b - a) of K_c[a][b]; stored as the contiguous row
+// A27[slot][delta * 6 + entry] at the node's compact slot.  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
 // and the data right-hand side b_i gathered from the cells.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R,
@@ -379,11 +379,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
       b[1] += bc[1];
       b[2] += bc[2];
     }
-    const size_t cap = L.capA;
+    T* __restrict__ row_out = A27 + (size_t)slot * kA27Row;
 #pragma unroll
     for (int dl = 0; dl < 27; ++dl)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) A27[(size_t)(dl * 6 + k) * cap + slot] = acc[dl][k];
+      for (int k = 0; k < 6; ++k) row_out[dl * 6 + k] = acc[dl][k];
+    row_out[162] = T(0);
+    row_out[163] = T(0);
     dg[0] = acc[13][0];
     dg[1] = acc[13][3];
     dg[2] = acc[13][5];

@@ -159,15 +159,16 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
   o1 = w2 * l1;
   o2 = w2 * l2;
   if (slot >= 0) {
-    const size_t cap = L.capA;
-    const T* __restrict__ A = L.A27 + slot;
+    // the node's 27 blocks are one contiguous, 16-byte aligned row: adjacent
+    // entries load as 16-byte vectors
+    const T* __restrict__ A =
+        static_cast<const T*>(__builtin_assume_aligned(L.A27 + (size_t)slot * kA27Row, 16));
 #pragma unroll
     for (int dl = 0; dl < 27; ++dl) {
       const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
       const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
-      const T* __restrict__ blk = A + (size_t)dl * 6 * cap;
-      const T s0 = blk[0], s1 = blk[cap], s2 = blk[2 * cap], s3 = blk[3 * cap],
-              s4 = blk[4 * cap], s5 = blk[5 * cap];
+      const T* __restrict__ blk = A + dl * 6;
+      const T s0 = blk[0], s1 = blk[1], s2 = blk[2], s3 = blk[3], s4 = blk[4], s5 = blk[5];
       const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
       o0 += s0 * q0 + s1 * q1 + s2 * q2;
       o1 += s1 * q0 + s3 * q1 + s4 * q2;

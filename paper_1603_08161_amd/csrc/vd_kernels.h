@@ -11,6 +11,10 @@ namespace vd {
 
 // Device-resident scalars of one level.  Written only by the last block of a
 // reduction kernel (or by a single thread), read by the next kernel.
+// Row of a node's 27 symmetric 3x3 data blocks in A27: 27 * 6 entries,
+// padded so that every row starts 16-byte aligned (656 B in float32).
+constexpr int kA27Row = 164;
+
 struct Scalars {
   double rz;      // r^T D^-1 r of the current CG iterate
   double pap;     // p^T A p
@@ -60,7 +64,8 @@ struct LevelView {
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
   const int* node_slot; // node -> slot in A27, -1 if no data term touches it
-  const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
+  const T* A27;         // [capA][kA27Row] data blocks of each node's row of A: per
+                        // node slot, 27 offsets x 6 entries, contiguous
   int capA;             // slots allocated in A27
   // constraint rows of the current frame (SoA with stride sc->rows)
   const int* row_cell;
