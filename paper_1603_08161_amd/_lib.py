@@ -118,8 +118,8 @@ class VDError(RuntimeError):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
-            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
-            "g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+            f"{LIB_PATH} is missing: build it with `python paper_1603_08161_amd/build.py` "
+            "(hipcc, gfx950). There is no CPU fallback.")
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     sig = {
