@@ -333,13 +333,14 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
 
 // Per node: the data part of row i of A as a 27-point block stencil,
 // A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
-// = corner b, delta = b - a) of K_c[a][b]; stored as the contiguous row
-// A27[slot][delta * 6 + entry] at the node's compact slot.  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
+// = corner b, delta = b - a) of K_c[a][b]; stored at the node's compact slot
+// both SoA [27*6][capA] (lanes holding consecutive slots read coalesced) and
+// as a contiguous row A27r[slot][delta * 6 + entry] (16-byte vector loads).  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
 // and the data right-hand side b_i gathered from the cells.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R,
                                                            const int* flags, const int* scan,
-                                                           int* node_slot, T* A27) {
+                                                           int* node_slot, T* A27, T* A27r) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.N) return;
   const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
@@ -379,11 +380,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
       b[1] += bc[1];
       b[2] += bc[2];
     }
-    T* __restrict__ row_out = A27 + (size_t)slot * kA27Row;
+    const size_t cap = L.capA;
+    T* __restrict__ row_out = A27r + (size_t)slot * kA27Row;
 #pragma unroll
     for (int dl = 0; dl < 27; ++dl)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) row_out[dl * 6 + k] = acc[dl][k];
+      for (int k = 0; k < 6; ++k) {
+        A27[(size_t)(dl * 6 + k) * cap + slot] = acc[dl][k];
+        row_out[dl * 6 + k] = acc[dl][k];
+      }
     row_out[162] = T(0);
     row_out[163] = T(0);
     dg[0] = acc[13][0];
@@ -401,8 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
 
 template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
-                                 const int* scan, int* node_slot, T* A27, hipStream_t s) {
-  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R, flags, scan, node_slot, A27);
+                                 const int* scan, int* node_slot, T* A27, T* A27r,
+                                 hipStream_t s) {
+  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R, flags, scan, node_slot, A27,
+                                                          A27r);
   return hipGetLastError();
 }
 
@@ -576,7 +583,8 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_build_cells<T>(const LevelView<T>&, const RowView<T>&, T*, int,    \
                                             hipStream_t);                                       \
   template hipError_t launch_assemble_nodes<T>(const LevelView<T>&, const RowView<T>&,          \
-                                               const int*, const int*, int*, T*, hipStream_t);  \
+                                               const int*, const int*, int*, T*, T*,         \
+                                               hipStream_t);                                    \
   template hipError_t launch_node_flags<T>(const LevelView<T>&, int*, hipStream_t);             \
   template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \
                                          const float*, const float*, int, int*, hipStream_t);   \

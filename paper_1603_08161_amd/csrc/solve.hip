@@ -130,7 +130,10 @@ struct TilePos {
 // A p at own node c (tile-local) / i (global) from the tile's p in LDS:
 // the ARAP Laplacian plus the node's 27-point data blocks at A27 slot `slot`
 // (-1: no data term touches the node).
-template <typename T, typename TL>
+// ROWS: read the data blocks from the contiguous rows (16-byte vector loads,
+// best when few lanes of a wave carry data) instead of the SoA copy (lanes
+// with consecutive slots coalesce).
+template <typename T, typename TL, bool ROWS = false>
 __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
                                          int gx, int gy, int gz, int slot, T& o0, T& o1,
                                          T& o2) {
@@ -158,17 +161,30 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
   o0 = w2 * l0;
   o1 = w2 * l1;
   o2 = w2 * l2;
-  if (slot >= 0) {
-    // the node's 27 blocks are one contiguous, 16-byte aligned row: adjacent
-    // entries load as 16-byte vectors
+  if (ROWS && slot >= 0) {
     const T* __restrict__ A =
-        static_cast<const T*>(__builtin_assume_aligned(L.A27 + (size_t)slot * kA27Row, 16));
+        static_cast<const T*>(__builtin_assume_aligned(L.A27r + (size_t)slot * kA27Row, 16));
 #pragma unroll
     for (int dl = 0; dl < 27; ++dl) {
       const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
       const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
       const T* __restrict__ blk = A + dl * 6;
       const T s0 = blk[0], s1 = blk[1], s2 = blk[2], s3 = blk[3], s4 = blk[4], s5 = blk[5];
+      const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
+      o0 += s0 * q0 + s1 * q1 + s2 * q2;
+      o1 += s1 * q0 + s3 * q1 + s4 * q2;
+      o2 += s2 * q0 + s4 * q1 + s5 * q2;
+    }
+  } else if (slot >= 0) {
+    const size_t cap = L.capA;
+    const T* __restrict__ A = L.A27 + slot;
+#pragma unroll
+    for (int dl = 0; dl < 27; ++dl) {
+      const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
+      const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
+      const T* __restrict__ blk = A + (size_t)dl * 6 * cap;
+      const T s0 = blk[0], s1 = blk[cap], s2 = blk[2 * cap], s3 = blk[3 * cap],
+              s4 = blk[4 * cap], s5 = blk[5 * cap];
       const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
       o0 += s0 * q0 + s1 * q1 + s2 * q2;
       o1 += s1 * q0 + s3 * q1 + s4 * q2;
@@ -316,7 +332,10 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& 
 
 // One CG iteration m on the tile of workgroup w (body of k_cg and of the
 // persistent k_cg_loop).
-template <typename T, typename TL, bool FIRST>
+// PF: load the own nodes' slot, preconditioner, displacement and previous
+// direction together with the halo (shorter dependent chain, more registers)
+// instead of at their use.
+template <typename T, typename TL, bool FIRST, bool PF = true>
 __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
                                         T (&sr)[3][TL::HALO]) {
   const LevelView<T>& L = w.L;
@@ -381,7 +400,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       own_d[kk][a] = T(0);
       own_pp[kk][a] = T(0);
     }
-    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+    if (PF && in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
 #pragma unroll
@@ -421,7 +440,10 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       for (int a = 0; a < 3; ++a) {
         const size_t j = a * N + hi[h];
         p_out[j] = p3[a];
-        if (!FIRST) r_out[j] = r3[a];
+        if (!FIRST) {
+          r_out[j] = r3[a];
+          if (!PF) L.d[j] += alpha * hp[h][a];
+        }
       }
     }
   }
@@ -436,13 +458,15 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
-    apply_at<T, TL>(L, sp, c, gx, gy, gz, own_slot[kk], o[0], o[1], o[2]);
+    apply_at<T, TL, PF>(L, sp, c, gx, gy, gz, PF ? own_slot[kk] : L.node_slot[i], o[0], o[1],
+                        o[2]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const size_t j = a * N + i;
       ap_out[j] = o[a];
-      if (!FIRST) L.d[j] = own_d[kk][a] + alpha * own_pp[kk][a];
-      const double q = (double)own_q[kk][a], r = (double)sr[a][c], p = (double)sp[a][c];
+      if (!FIRST && PF) L.d[j] = own_d[kk][a] + alpha * own_pp[kk][a];
+      const double q = (double)(PF ? own_q[kk][a] : dinv[j]), r = (double)sr[a][c],
+                   p = (double)sp[a][c];
       const double ap = (double)o[a];
       part[0] += r * q * r;
       part[1] += p * ap;
@@ -460,6 +484,21 @@ __global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   cg_body<T, TL, FIRST>(w, m, sp, sr);
 }
+
+// The same iteration with the own-node values loaded at their use: fewer
+// registers, so more resident waves.  For grids larger than one round of
+// workgroups (batched lattices) occupancy hides more latency than the
+// register-held prefetches of k_cg.
+template <typename T, typename TL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cg_occ(Dispatch<T> D, int m) {
+  __shared__ T sp[3][TL::HALO];
+  __shared__ T sr[3][TL::HALO];
+  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
+  cg_body<T, TL, FIRST, false>(w, m, sp, sr);
+}
+
+// Workgroups that fit in one round on 256 CUs at the register use of k_cg.
+constexpr int kOneRoundBlocks = 1024;
 
 // Grid barrier of a launch whose workgroups are all resident: every
 // workgroup publishes its writes (agent-scope release), counts itself in,
@@ -545,8 +584,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
 
 template <typename T, typename TL>
 void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s) {
-  if (m == 0) k_cg<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
-  else k_cg<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+  if (D.blocks > kOneRoundBlocks) {
+    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
+    else k_cg_occ<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+  } else {
+    if (m == 0) k_cg<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
+    else k_cg<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+  }
 }
 
 template <typename T>

@@ -11,8 +11,8 @@ namespace vd {
 
 // Device-resident scalars of one level.  Written only by the last block of a
 // reduction kernel (or by a single thread), read by the next kernel.
-// Row of a node's 27 symmetric 3x3 data blocks in A27: 27 * 6 entries,
-// padded so that every row starts 16-byte aligned (656 B in float32).
+// Row of a node's 27 symmetric 3x3 data blocks in LevelView::A27r: 27 * 6
+// entries, padded so that every row starts 16-byte aligned.
 constexpr int kA27Row = 164;
 
 struct Scalars {
@@ -64,8 +64,8 @@ struct LevelView {
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
   const int* node_slot; // node -> slot in A27, -1 if no data term touches it
-  const T* A27;         // [capA][kA27Row] data blocks of each node's row of A: per
-                        // node slot, 27 offsets x 6 entries, contiguous
+  const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
+  const T* A27r;        // the same blocks as contiguous rows [capA][kA27Row]
   int capA;             // slots allocated in A27
   // constraint rows of the current frame (SoA with stride sc->rows)
   const int* row_cell;
@@ -135,7 +135,8 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s);
 
 template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
-                                 const int* scan, int* node_slot, T* A27, hipStream_t s);
+                                 const int* scan, int* node_slot, T* A27, T* A27r,
+                                 hipStream_t s);
 
 // ---- solve (solve.hip) ------------------------------------------------------
 enum StencilMode { kModeRhs = 1, kModeApply = 2, kModeGrad = 3 };
