@@ -228,3 +228,59 @@ def test_warm_start_keeps_a_better_prediction_and_hits_the_target():
     rp = lat.solve_frame(report=True, energy_target=e_plain * 1.001, max_gn=5)
     assert rp["gn_done"] >= rep["gn_done"]
     assert rp["target_reached"] == 0 or rp["energy"][0] <= e_plain * 1.001
+
+
+@pytest.mark.parametrize("dims", [(3, 2, 1), (1, 1, 1), (5, 1, 4)])
+def test_forward_degenerate_grid_sizes(dims):
+    """Axes of one or two nodes (stride-2 levels collapse to one node, the
+    up-sampling crops): still the oracle's network."""
+    from paper_1603_08161_amd import Net
+    v = _params(15)
+    nt = Net(dims)
+    nt.set_params(v)
+    bits = _input(16, dims, 1)
+    out = nt.forward(bits)
+    ref, _ = _oracle_forward(_oracle_params(v), bits[0], dims)
+    n = dims[0] * dims[1] * dims[2]
+    assert rel_err(out[0], ref.reshape(3, n)) < 1e-2
+
+
+def test_features_fp64_lattice_and_no_dense_samples():
+    """The float64 lattice builds the same features; without dense samples
+    the residual and validity channels are zero."""
+    scene = make_config0(0)
+    g = grids_of(scene)[-1]
+    rng = np.random.default_rng(17)
+    pos, rot = random_state(g, rng, amp=0.2)
+    lat = make_lattice(scene, precision="fp64")
+    lat.set_state(pos, rot)
+    x = lat.warm_features()
+    ref = oracle_features(g, oracle_cons(scene), pos.astype(np.float64))
+    got = _from_bits(x.reshape(-1, 8))
+    rb = onet.bf16_round(ref)
+    np.testing.assert_allclose(got[:, :6], rb[:, :6], rtol=2 ** -7, atol=1e-5)
+    assert np.array_equal(got[:, 7], ref[:, 7])
+    scale = np.abs(ref[:, 6]).max()
+    np.testing.assert_allclose(got[:, 6], rb[:, 6], rtol=2 ** -7, atol=1e-5 * scale)
+    z = np.zeros((0, 3), np.float32)
+    lat.set_constraints(z, z, z, None, scene.sparse_canon, scene.sparse_target)
+    x0 = _from_bits(lat.warm_features().reshape(-1, 8))
+    assert np.all(x0[:, 6:] == 0.0)
+
+
+def test_warm_start_judge_fp64():
+    """The judge in the float64 mode: a garbage prediction is dropped and the
+    frame equals the plain solve bit for bit."""
+    scene, lat = _sequence_lattice(precision="fp64")
+    pos0, rot0 = lat.get_state()
+    lat.set_scene(make_config0(2))
+    lat.set_state(pos0, rot0)
+    lat.solve_frame()
+    pos_plain, _ = lat.get_state()
+    lat.set_state(pos0, rot0)
+    bad = np.random.default_rng(18).normal(scale=20.0, size=(3, pos0.shape[0])).astype(np.float32)
+    rep = lat.solve_frame(report=True, init_delta=bad)
+    assert rep["warm_used"] == 0
+    np.testing.assert_array_equal(lat.get_state()[0], pos_plain)
+    with pytest.raises(Exception):
+        lat.solve_frame(init_delta=np.full((3, pos0.shape[0]), np.nan, np.float32))
