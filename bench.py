@@ -152,7 +152,7 @@ def main() -> int:
     lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent, profile=True)
     lat.set_constraints(*inputs)
     tiles, tile_us = lat.tune(iters=10)
-    print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4]: "
+    print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4, 32x8x4/1024]: "
           + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us), flush=True)
 
     def step():

@@ -98,6 +98,7 @@ extern "C" {
                                          VD_FLAG_PERSIST) */
 
 #define VD_MAX_LEVELS 4
+#define VD_TILE_KINDS 4
 #define VD_MAX_TRACE 512
 
 typedef struct vd_lattice vd_lattice;
@@ -122,7 +123,8 @@ typedef struct {
   uint32_t flags;                   /* VD_FLAG_* */
   int32_t tile[VD_MAX_LEVELS];      /* stencil tile per level: 0 = library
                                        default, 1 = 8x8x4, 2 = 8x8x8,
-                                       3 = 32x8x4 (see vd_tune) */
+                                       3 = 32x8x4 (256 threads), 4 = 32x8x4
+                                       (1024 threads) (see vd_tune) */
 } vd_lattice_desc;
 
 /* Correspondences of one frame (Sec. 5, used by eqs. (2)-(3)).
@@ -268,9 +270,10 @@ const char* vd_strerror(int code);
 /* Autotuner of the stencil tile shape (the brick each workgroup stages in
  * LDS).  For every level it times `iters` CG iterations with each tile kind
  * on the current constraints (the state is saved and restored), keeps the
- * fastest for later frames and reports it in tile_out[level] (1..3, as in
+ * fastest for later frames and reports it in tile_out[level] (1..4, as in
  * vd_lattice_desc.tile) with the mean microseconds per CG iteration of each
- * kind in us_out[3 * level + kind - 1] (either pointer may be NULL).
+ * kind in us_out[VD_TILE_KINDS * level + kind - 1] (either pointer may be
+ * NULL).
  * VD_ESTATE if no constraints were set.  Synchronous. */
 int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out);
 

@@ -35,6 +35,7 @@ VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
 VD_REPORT_WARM_REJECTED = 8
 VD_REPORT_BARRIER_TIMEOUT = 16
 VD_MAX_LEVELS = 4
+VD_TILE_KINDS = 4
 VD_MAX_TRACE = 512
 
 EXPORTED = (
@@ -370,11 +371,12 @@ class Lattice:
         """Run the library's tile autotuner; returns (tiles per level, mean us per
         CG iteration [level][kind])."""
         tiles = (C.c_int32 * VD_MAX_LEVELS)()
-        us = (C.c_double * (3 * VD_MAX_LEVELS))()
+        us = (C.c_double * (VD_TILE_KINDS * VD_MAX_LEVELS))()
         _check(_lib.vd_tune(self._h, int(iters), tiles, us), "vd_tune")
         n = self.num_levels
         return ([int(tiles[k]) for k in range(n)],
-                [[float(us[3 * k + j]) for j in range(3)] for k in range(n)])
+                [[float(us[VD_TILE_KINDS * k + j]) for j in range(VD_TILE_KINDS)]
+                 for k in range(n)])
 
     def get_energy(self) -> np.ndarray:
         out = (C.c_double * 4)()

@@ -15,6 +15,8 @@
 #include "vd_device.h"
 #include "vd_kernels.h"
 
+static_assert(VD_TILE_KINDS == vd::kTileKinds, "tile kinds of vd.h and the kernels differ");
+
 namespace vd {
 namespace {
 
@@ -677,7 +679,7 @@ class Solver final : public ISolver {
           VD_TRY(hipEventElapsedTime(&ms, e0, e1));
         }
         const double us = 1000.0 * ms / iters;
-        if (us_out) us_out[3 * l + kind] = us;
+        if (us_out) us_out[VD_TILE_KINDS * l + kind] = us;
         if (us < best) {
           best = us;
           best_kind = kind;

@@ -65,11 +65,11 @@ __device__ __forceinline__ int energy_blocks_dev(const LevelView<T>& L) {
 }
 
 // Block sums of K values written to out[k * stride + local].
-template <int K>
+template <int K, int NT = kBlock>
 __device__ __forceinline__ void write_partials(double (&v)[K], double* out, int stride,
                                                int local) {
-  __shared__ double lds[K * (kBlock / kWave)];
-  block_sum<K>(v, lds);
+  __shared__ double lds[K * (NT / kWave)];
+  block_sum<K, NT>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) out[(size_t)k * stride + local] = v[k];
@@ -89,6 +89,7 @@ int tile_blocks(int kind, int nx, int ny, int nz) {
   switch (kind) {
     case 1: return nb(TileM::TX, TileM::TY, TileM::TZ);
     case 2: return nb(TileW::TX, TileW::TY, TileW::TZ);
+    case 3: return nb(TileX::TX, TileX::TY, TileX::TZ);
     default: return nb(TileS::TX, TileS::TY, TileS::TZ);
   }
 }
@@ -197,7 +198,7 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
 //            gradient J^T r; r = -g is stored (the CG residual r_0).
 // kModeApply / kModeGrad : A p or g written to `out` (test entry points).
 template <typename T, typename TL, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
+__global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
                                                     T* __restrict__ out) {
   __shared__ T sp[3][TL::HALO];
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __re
   const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
   // the CG solve that follows a gradient pass counts its grid barrier from 0
   if (MODE == kModeRhs && w.local == 0 && threadIdx.x == 0) L.sc->bar = 0u;
-  for (int k = threadIdx.x; k < TL::HALO; k += kBlock) {
+  for (int k = threadIdx.x; k < TL::HALO; k += TL::NT) {
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     T v0 = T(0), v1 = T(0), v2 = T(0);
@@ -279,9 +280,9 @@ __global__ __launch_bounds__(kBlock) void k_stencil(Dispatch<T> D, const T* __re
 template <typename T, typename TL>
 void launch_stencil_t(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s) {
   switch (mode) {
-    case kModeRhs: k_stencil<T, TL, kModeRhs><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
-    case kModeApply: k_stencil<T, TL, kModeApply><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
-    default: k_stencil<T, TL, kModeGrad><<<D.blocks, kBlock, 0, s>>>(D, pin, out); break;
+    case kModeRhs: k_stencil<T, TL, kModeRhs><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
+    case kModeApply: k_stencil<T, TL, kModeApply><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
+    default: k_stencil<T, TL, kModeGrad><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
   }
 }
 
@@ -293,6 +294,7 @@ hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, 
   switch (D.one.tile) {
     case 1: launch_stencil_t<T, TileM>(mode, D, pin, out, s); break;
     case 2: launch_stencil_t<T, TileW>(mode, D, pin, out, s); break;
+    case 3: launch_stencil_t<T, TileX>(mode, D, pin, out, s); break;
     default: launch_stencil_t<T, TileS>(mode, D, pin, out, s); break;
   }
   return hipGetLastError();
@@ -316,11 +318,11 @@ hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, 
 // halo inputs are loaded before the scalar reduction so that both latencies
 // overlap.  The last iteration's step is applied by k_cg_final.
 
-template <typename T>
+template <typename T, int NT = kBlock>
 __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& beta,
                                            Scalars* sc, bool count_guard) {
   double v[4];
-  sum_partials_k<4>(s, n, v);
+  sum_partials_k<4, NT>(s, n, v);
   const double rz = v[0], pap = v[1], apdr = v[2], apdap = v[3];
   const double a = pap > 0.0 ? rz / pap : 0.0;
   double rz_new = rz - 2.0 * a * apdr + a * a * apdap;
@@ -357,7 +359,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   bool hin[TL::HPT];
 #pragma unroll
   for (int h = 0; h < TL::HPT; ++h) {
-    const int k = threadIdx.x + h * kBlock;
+    const int k = threadIdx.x + h * TL::NT;
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     hin[h] = k < TL::HALO && in_box(gx, gy, gz, L.nx, L.ny, L.nz);
@@ -415,11 +417,11 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   }
   // 2. CG scalars of the previous iterate
   T alpha = T(0), beta = T(0);
-  if (!FIRST) cg_scalars<T>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  if (!FIRST) cg_scalars<T, TL::NT>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
   // 3. r_m, p_m into LDS; own nodes also store r_m, p_m and step d
 #pragma unroll
   for (int h = 0; h < TL::HPT; ++h) {
-    const int k = threadIdx.x + h * kBlock;
+    const int k = threadIdx.x + h * TL::NT;
     if (k >= TL::HALO) continue;
     T p3[3], r3[3];
 #pragma unroll
@@ -474,11 +476,11 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       part[3] += ap * q * ap;
     }
   }
-  write_partials<4>(part, s_out, w.count, w.local);
+  write_partials<4, TL::NT>(part, s_out, w.count, w.local);
 }
 
 template <typename T, typename TL, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
+__global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
@@ -490,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_cg(Dispatch<T> D, int m) {
 // workgroups (batched lattices) occupancy hides more latency than the
 // register-held prefetches of k_cg.
 template <typename T, typename TL, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_cg_occ(Dispatch<T> D, int m) {
+__global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
@@ -532,7 +534,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const bool odd = (last & 1) != 0;
   T alpha, beta;
-  cg_scalars<T>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  cg_scalars<T, TL::NT>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
   const size_t N = L.N;
   const T* __restrict__ p = odd ? L.pb : L.pa;
   T* __restrict__ d = L.d;
@@ -550,7 +552,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
 
 // All iterations of one CG solve (single lattice, every tile resident).
 template <typename T, typename TL>
-__global__ __launch_bounds__(kBlock) void k_cg_loop(Dispatch<T> D, int iters) {
+__global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
@@ -584,12 +586,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
 
 template <typename T, typename TL>
 void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s) {
-  if (D.blocks > kOneRoundBlocks) {
-    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
-    else k_cg_occ<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+  if ((long)D.blocks * TL::NT > (long)kOneRoundBlocks * kBlock) {
+    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m);
+    else k_cg_occ<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m);
   } else {
-    if (m == 0) k_cg<T, TL, true><<<D.blocks, kBlock, 0, s>>>(D, m);
-    else k_cg<T, TL, false><<<D.blocks, kBlock, 0, s>>>(D, m);
+    if (m == 0) k_cg<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m);
+    else k_cg<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m);
   }
 }
 
@@ -599,6 +601,7 @@ hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s) {
   switch (D.one.tile) {
     case 1: launch_cg_t<T, TileM>(m, D, s); break;
     case 2: launch_cg_t<T, TileW>(m, D, s); break;
+    case 3: launch_cg_t<T, TileX>(m, D, s); break;
     default: launch_cg_t<T, TileS>(m, D, s); break;
   }
   return hipGetLastError();
@@ -617,9 +620,10 @@ hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s) {
   if (D.n != 1 || D.blocks > kPersistMaxTiles || D.blocks != D.one.ntiles)
     return hipErrorInvalidValue;
   switch (D.one.tile) {
-    case 1: k_cg_loop<T, TileM><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
-    case 2: k_cg_loop<T, TileW><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
-    default: k_cg_loop<T, TileS><<<D.blocks, kBlock, 0, s>>>(D, iters); break;
+    case 1: k_cg_loop<T, TileM><<<D.blocks, TileM::NT, 0, s>>>(D, iters); break;
+    case 2: k_cg_loop<T, TileW><<<D.blocks, TileW::NT, 0, s>>>(D, iters); break;
+    case 3: k_cg_loop<T, TileX><<<D.blocks, TileX::NT, 0, s>>>(D, iters); break;
+    default: k_cg_loop<T, TileS><<<D.blocks, TileS::NT, 0, s>>>(D, iters); break;
   }
   return hipGetLastError();
 }

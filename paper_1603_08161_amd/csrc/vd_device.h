@@ -19,23 +19,26 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kXcds = 8;      // MI355X: 8 accelerator dies, workgroups dealt round-robin
 
 // Tiles of the stencil kernels: TX x TY x TZ nodes staged in LDS with a
-// one-node halo; 256 threads, each owning NPT consecutive nodes along z.
-template <int TX_, int TY_, int TZ_>
+// one-node halo; NT threads, each owning NPT consecutive nodes along z.
+template <int TX_, int TY_, int TZ_, int NT_ = kBlock>
 struct Tile {
-  static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_, NT = NT_;
   static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
   static constexpr int HALO = HX * HY * HZ;
-  static constexpr int ZG = 256 / (TX * TY);     // thread layers along z
-  static constexpr int NPT = TZ / ZG;            // nodes per thread
-  static constexpr int HPT = (HALO + 255) / 256;  // halo nodes staged per thread
+  static constexpr int ZG = NT / (TX * TY);          // thread layers along z
+  static constexpr int NPT = TZ / ZG;                // nodes per thread
+  static constexpr int HPT = (HALO + NT - 1) / NT;   // halo nodes staged per thread
 };
 // Tile kinds: small (most workgroups, best latency hiding), medium (half the
 // block partials and 1.95x instead of 2.34x halo reads), wide (128-byte rows
-// along x, 4x fewer block partials, one workgroup per CU on 64^3).
+// along x, 4x fewer block partials, 4 nodes per thread), wide with one node
+// per thread (the wide tile on 1024 threads: its halo rows cover about half
+// as many cache lines per wave load as the small tile's).
 using TileS = Tile<8, 8, 4>;
 using TileM = Tile<8, 8, 8>;
 using TileW = Tile<32, 8, 4>;
-constexpr int kTileKinds = 3;
+using TileX = Tile<32, 8, 4, 1024>;
+constexpr int kTileKinds = 4;
 
 // Maps the hardware workgroup id to a logical tile id so that each XCD gets a
 // contiguous range of tiles (neighbouring tiles then share that XCD's L2).
@@ -56,14 +59,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum K values over the block; the result is valid in thread 0.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* K * kBlock/kWave */) {
+template <int K, int NT = kBlock>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* K * NT/kWave */) {
+  constexpr int NW = NT / kWave;
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) lds[k * (kBlock / kWave) + wid] = v[k];
+    for (int k = 0; k < K; ++k) lds[k * NW + wid] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -71,7 +75,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* K * kBl
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < kBlock / kWave; ++w) s += lds[k * (kBlock / kWave) + w];
+      for (int w = 0; w < NW; ++w) s += lds[k * NW + w];
       v[k] = s;
     }
   }
@@ -103,15 +107,16 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 
 // Sums of K partial arrays p + k*n (k < K) in one pass (one round of loads),
 // identical in every block; result valid in every thread.
-template <int K>
+template <int K, int NT = kBlock>
 __device__ __forceinline__ void sum_partials_k(const double* __restrict__ p, int n,
                                                double (&out)[K]) {
-  __shared__ double lds[K * (kBlock / kWave)];
+  constexpr int NW = NT / kWave;
+  __shared__ double lds[K * NW];
   __shared__ double total[K];
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < n; b += kBlock) {
+  for (int b = threadIdx.x; b < n; b += NT) {
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += p[(size_t)k * n + b];
   }
@@ -120,13 +125,13 @@ __device__ __forceinline__ void sum_partials_k(const double* __restrict__ p, int
   for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) lds[k * (kBlock / kWave) + wid] = acc[k];
+    for (int k = 0; k < K; ++k) lds[k * NW + wid] = acc[k];
   }
   __syncthreads();
   if (threadIdx.x < K) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) s += lds[threadIdx.x * (kBlock / kWave) + w];
+    for (int w = 0; w < NW; ++w) s += lds[threadIdx.x * NW + w];
     total[threadIdx.x] = s;
   }
   __syncthreads();

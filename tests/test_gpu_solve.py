@@ -179,7 +179,7 @@ def test_empty_constraints():
     assert rep["energy"][0] == 0.0
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_every_tile_kind_matches_replica(tile):
     scene = make_tiny(seed=7, dims=(37, 21, 18), num_levels=3, gn=3, pcg=8, n_dense=1500,
                       n_sparse=30, spacing=0.5, origin=(0.0, 0.0, 0.0))
