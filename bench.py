@@ -52,11 +52,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str = "traffic_k_cg_frame64.md"):
-    """HBM bytes per launch of the 64^3 CG-iteration kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
-    counters on a plain copy), or None if the summary is missing or the
-    kernel's sources changed since the counters were taken."""
+def measured_traffic(tile: int, name: str = "traffic_k_cg_frame64.md"):
+    """HBM bytes per launch of the 64^3 CG-iteration kernel with stencil tile
+    `tile` (1..4) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the same counters on a plain copy), or None if the
+    summary is missing, has no entry for that tile, or the kernel's sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -69,7 +70,7 @@ def measured_traffic(name: str = "traffic_k_cg_frame64.md"):
     if kv.get("source_sha") != kernel_source_sha():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch_tile{tile}"])
     except (KeyError, ValueError):
         return None
 
@@ -255,7 +256,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(tiles[-1]),
             "bytes_per_launch": nbytes,
             "mean_us": cg_a_us,
             "timing": "device clock stamps captured in the frame graph around the 64^3 "
