@@ -269,7 +269,8 @@ const char* vd_strerror(int code);
 
 /* Autotuner of the stencil tile shape (the brick each workgroup stages in
  * LDS).  For every level it times `iters` CG iterations with each tile kind
- * on the current constraints (the state is saved and restored), keeps the
+ * on the current constraints (the state is saved and restored; one warm-up
+ * pass, then the fastest of three timed passes), keeps the
  * fastest for later frames and reports it in tile_out[level] (1..4, as in
  * vd_lattice_desc.tile) with the mean microseconds per CG iteration of each
  * kind in us_out[VD_TILE_KINDS * level + kind - 1] (either pointer may be
