@@ -335,8 +335,10 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
 // A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
 // = corner b, delta = b - a) of K_c[a][b]; stored at the node's compact slot
 // both SoA [27*6][capA] (lanes holding consecutive slots read coalesced) and
-// as a contiguous row A27r[slot][delta * 6 + entry] (16-byte vector loads).  Also the Jacobi diagonal 2 w_r |N_i| + diag(A27[0]),
-// and the data right-hand side b_i gathered from the cells.
+// as a row A27r[slot][kA27Row] in three 16-byte-aligned parts by dz (one part
+// is one lane's share of the node in the CG iteration).  Also the Jacobi
+// diagonal 2 w_r |N_i| + diag(A27[0]), and the data right-hand side b_i
+// gathered from the cells.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R,
                                                            const int* flags, const int* scan,
@@ -387,10 +389,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         A27[(size_t)(dl * 6 + k) * cap + slot] = acc[dl][k];
-        row_out[dl * 6 + k] = acc[dl][k];
+        row_out[(dl / 9) * kA27Part + (dl % 9) * 6 + k] = acc[dl][k];
       }
-    row_out[162] = T(0);
-    row_out[163] = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int k = 54; k < kA27Part; ++k) row_out[m * kA27Part + k] = T(0);
     dg[0] = acc[13][0];
     dg[1] = acc[13][3];
     dg[2] = acc[13][5];

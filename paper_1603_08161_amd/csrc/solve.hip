@@ -130,11 +130,8 @@ struct TilePos {
 
 // A p at own node c (tile-local) / i (global) from the tile's p in LDS:
 // the ARAP Laplacian plus the node's 27-point data blocks at A27 slot `slot`
-// (-1: no data term touches the node).
-// ROWS: read the data blocks from the contiguous rows (16-byte vector loads,
-// best when few lanes of a wave carry data) instead of the SoA copy (lanes
-// with consecutive slots coalesce).
-template <typename T, typename TL, bool ROWS = false>
+// (-1: no data term touches the node, or the caller adds it).
+template <typename T, typename TL>
 __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
                                          int gx, int gy, int gz, int slot, T& o0, T& o1,
                                          T& o2) {
@@ -162,21 +159,7 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
   o0 = w2 * l0;
   o1 = w2 * l1;
   o2 = w2 * l2;
-  if (ROWS && slot >= 0) {
-    const T* __restrict__ A =
-        static_cast<const T*>(__builtin_assume_aligned(L.A27r + (size_t)slot * kA27Row, 16));
-#pragma unroll
-    for (int dl = 0; dl < 27; ++dl) {
-      const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
-      const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
-      const T* __restrict__ blk = A + dl * 6;
-      const T s0 = blk[0], s1 = blk[1], s2 = blk[2], s3 = blk[3], s4 = blk[4], s5 = blk[5];
-      const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
-      o0 += s0 * q0 + s1 * q1 + s2 * q2;
-      o1 += s1 * q0 + s3 * q1 + s4 * q2;
-      o2 += s2 * q0 + s4 * q1 + s5 * q2;
-    }
-  } else if (slot >= 0) {
+  if (slot >= 0) {
     const size_t cap = L.capA;
     const T* __restrict__ A = L.A27 + slot;
 #pragma unroll
@@ -190,6 +173,105 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
       o0 += s0 * q0 + s1 * q1 + s2 * q2;
       o1 += s1 * q0 + s3 * q1 + s4 * q2;
       o2 += s2 * q0 + s4 * q1 + s5 * q2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// data part of A p in the CG iteration, shared by the workgroup
+// ---------------------------------------------------------------------------
+//
+// Only nodes near the observed surface carry data blocks, and they cluster in
+// a few waves.  Evaluated by its owner, a node's 27 blocks are a long chain of
+// row loads in one lane while most lanes idle, and the workgroup waits for its
+// busiest wave.  Instead every wave lists its own such nodes in LDS (a segment
+// per wave, in (k, lane) order) and, once the tile is staged, the workgroup's
+// lanes take (node, part) items: per wave and round 21 nodes, lanes 3n, 3n+1
+// and 3n+2 evaluating the blocks of dz = -1, 0, +1 of node n from that part of
+// the node's row (14 16-byte loads).  Lane 3n adds the three sums in fixed
+// order and leaves the result in LDS for the owner.  A node's sum does not
+// depend on which lane or round evaluates it, so every tile shape and both CG
+// forms give the same bits.
+
+constexpr int kPartsPerNode = 3;
+constexpr int kNodesPerWave = kWave / kPartsPerNode;  // 21; lane 63 idles
+
+template <typename T, typename TL>
+struct DataShare {
+  static constexpr int SEG = kWave * TL::NPT;  // list entries per wave
+  static constexpr int NW = TL::NT / kWave;
+  int slot[NW * SEG];
+  int node[NW * SEG];  // LDS tile index of the node
+  int cnt[NW];
+  T d[3][NW * SEG];    // data part of A p of list entry e
+};
+
+// List the calling wave's own nodes that carry data blocks; rank[k]: entry of
+// the thread's k-th node in the wave's segment (-1: none).
+template <typename T, typename TL>
+__device__ __forceinline__ void list_data_nodes(const int (&slot)[TL::NPT],
+                                                DataShare<T, TL>& ds, int (&rank)[TL::NPT]) {
+  using DS = DataShare<T, TL>;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < TL::NPT; ++k) {
+    const unsigned long long m = __ballot(slot[k] >= 0);
+    rank[k] = -1;
+    if (slot[k] >= 0) {
+      rank[k] = base + __popcll(m & below);
+      const int e = wv * DS::SEG + rank[k];
+      ds.slot[e] = slot[k];
+      ds.node[e] = TilePos<TL>::own(k);
+    }
+    base += __popcll(m);
+  }
+  if (lane == 0) ds.cnt[wv] = base;
+}
+
+// Data part of A p for every listed node of the workgroup (after the barrier
+// that publishes the lists and the tile's p); results in ds.d.
+template <typename T, typename TL>
+__device__ __forceinline__ void eval_data_nodes(const LevelView<T>& L,
+                                                const T (*sp)[TL::HALO],
+                                                DataShare<T, TL>& ds) {
+  using DS = DataShare<T, TL>;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int part = lane % kPartsPerNode, nl = lane / kPartsPerNode;
+  int total = 0;
+#pragma unroll
+  for (int u = 0; u < DS::NW; ++u) total += ds.cnt[u];
+  for (int r0 = 0; r0 < total; r0 += DS::NW * kNodesPerWave) {
+    const int v = r0 + wv * kNodesPerWave + nl;
+    T o0 = T(0), o1 = T(0), o2 = T(0);
+    int e = -1;
+    if (nl < kNodesPerWave && v < total) {
+      int u = 0, before = 0;
+      while (v >= before + ds.cnt[u]) before += ds.cnt[u++];
+      e = u * DS::SEG + (v - before);
+      const int cz = ds.node[e] + TL::HX * TL::HY * (part - 1);
+      const T* __restrict__ A = static_cast<const T*>(__builtin_assume_aligned(
+          L.A27r + (size_t)ds.slot[e] * kA27Row + part * kA27Part, 16));
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const int q = cz + (j % 3 - 1) + TL::HX * (j / 3 - 1);
+        const T* __restrict__ blk = A + j * 6;
+        const T s0 = blk[0], s1 = blk[1], s2 = blk[2], s3 = blk[3], s4 = blk[4], s5 = blk[5];
+        const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
+        o0 += s0 * q0 + s1 * q1 + s2 * q2;
+        o1 += s1 * q0 + s3 * q1 + s4 * q2;
+        o2 += s2 * q0 + s4 * q1 + s5 * q2;
+      }
+    }
+    const T a0 = __shfl_down(o0, 1, kWave), a1 = __shfl_down(o1, 1, kWave),
+            a2 = __shfl_down(o2, 1, kWave);
+    const T b0 = __shfl_down(o0, 2, kWave), b1 = __shfl_down(o1, 2, kWave),
+            b2 = __shfl_down(o2, 2, kWave);
+    if (part == 0 && e >= 0) {
+      ds.d[0][e] = (o0 + a0) + b0;
+      ds.d[1][e] = (o1 + a1) + b1;
+      ds.d[2][e] = (o2 + a2) + b2;
     }
   }
 }
@@ -339,7 +421,7 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& 
 // instead of at their use.
 template <typename T, typename TL, bool FIRST, bool PF = true>
 __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
-                                        T (&sr)[3][TL::HALO]) {
+                                        T (&sr)[3][TL::HALO], DataShare<T, TL>& ds) {
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
@@ -402,15 +484,17 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       own_d[kk][a] = T(0);
       own_pp[kk][a] = T(0);
     }
-    if (PF && in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
+      if (PF) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        own_q[kk][a] = dinv[a * N + i];
-        if (!FIRST) {
-          own_d[kk][a] = L.d[a * N + i];
-          own_pp[kk][a] = p_in[a * N + i];
+        for (int a = 0; a < 3; ++a) {
+          own_q[kk][a] = dinv[a * N + i];
+          if (!FIRST) {
+            own_d[kk][a] = L.d[a * N + i];
+            own_pp[kk][a] = p_in[a * N + i];
+          }
         }
       }
     }
@@ -418,6 +502,8 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   // 2. CG scalars of the previous iterate
   T alpha = T(0), beta = T(0);
   if (!FIRST) cg_scalars<T, TL::NT>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
+  int rank[TL::NPT];
+  list_data_nodes<T, TL>(own_slot, ds, rank);
   // 3. r_m, p_m into LDS; own nodes also store r_m, p_m and step d
 #pragma unroll
   for (int h = 0; h < TL::HPT; ++h) {
@@ -451,6 +537,8 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   }
   __syncthreads();
   // 4. A p_m on own nodes and the block partials of S_m
+  eval_data_nodes<T, TL>(L, sp, ds);
+  __syncthreads();
   double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < TL::NPT; ++kk) {
@@ -460,10 +548,11 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
-    apply_at<T, TL, PF>(L, sp, c, gx, gy, gz, PF ? own_slot[kk] : L.node_slot[i], o[0], o[1],
-                        o[2]);
+    apply_at<T, TL>(L, sp, c, gx, gy, gz, -1, o[0], o[1], o[2]);
+    const int e = (threadIdx.x / kWave) * DataShare<T, TL>::SEG + rank[kk];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      if (rank[kk] >= 0) o[a] += ds.d[a][e];
       const size_t j = a * N + i;
       ap_out[j] = o[a];
       if (!FIRST && PF) L.d[j] = own_d[kk][a] + alpha * own_pp[kk][a];
@@ -483,8 +572,9 @@ template <typename T, typename TL, bool FIRST>
 __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST>(w, m, sp, sr);
+  cg_body<T, TL, FIRST>(w, m, sp, sr, ds);
 }
 
 // The same iteration with the own-node values loaded at their use: fewer
@@ -495,8 +585,9 @@ template <typename T, typename TL, bool FIRST>
 __global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST, false>(w, m, sp, sr);
+  cg_body<T, TL, FIRST, false>(w, m, sp, sr, ds);
 }
 
 // Workgroups that fit in one round on 256 CUs at the register use of k_cg.
@@ -555,13 +646,14 @@ template <typename T, typename TL>
 __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   Scalars* sc = w.L.sc;
   for (int m = 0; m < iters; ++m) {
     if (m == 0)
-      cg_body<T, TL, true>(w, m, sp, sr);
+      cg_body<T, TL, true>(w, m, sp, sr, ds);
     else
-      cg_body<T, TL, false>(w, m, sp, sr);
+      cg_body<T, TL, false>(w, m, sp, sr, ds);
     grid_barrier(&sc->bar, (unsigned)(m + 1) * gridDim.x, &sc->bar_timeouts);
   }
   cg_final_tile<T, TL>(w, iters - 1);

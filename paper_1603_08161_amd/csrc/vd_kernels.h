@@ -11,9 +11,13 @@ namespace vd {
 
 // Device-resident scalars of one level.  Written only by the last block of a
 // reduction kernel (or by a single thread), read by the next kernel.
-// Row of a node's 27 symmetric 3x3 data blocks in LevelView::A27r: 27 * 6
-// entries, padded so that every row starts 16-byte aligned.
-constexpr int kA27Row = 164;
+// Row of a node's 27 symmetric 3x3 data blocks in LevelView::A27r: three
+// parts (the 9 blocks of offset dz = -1, 0, +1, in (dx, dy) order), each 9 * 6
+// entries padded to kA27Part so that every part starts 16-byte aligned; entry
+// k of block delta = (dx, dy, dz) sits at (dz + 1) * kA27Part + ((dx + 1) +
+// 3 (dy + 1)) * 6 + k.  The two pad entries of a part hold 0.
+constexpr int kA27Part = 56;
+constexpr int kA27Row = 3 * kA27Part;
 
 struct Scalars {
   double rz;      // r^T D^-1 r of the current CG iterate
@@ -65,7 +69,7 @@ struct LevelView {
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
   const int* node_slot; // node -> slot in A27, -1 if no data term touches it
   const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
-  const T* A27r;        // the same blocks as contiguous rows [capA][kA27Row]
+  const T* A27r;        // the same blocks as rows [capA][kA27Row] (three parts by dz)
   int capA;             // slots allocated in A27
   // constraint rows of the current frame (SoA with stride sc->rows)
   const int* row_cell;
