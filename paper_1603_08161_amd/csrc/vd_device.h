@@ -52,10 +52,37 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // reductions (float64 sums, fixed order => bitwise deterministic)
 // ---------------------------------------------------------------------------
 
+// Value of lane CTRL's DPP source (data-parallel primitive: a lane
+// permutation inside rows of 16 lanes, done in the vector ALU without the
+// LDS crossbar that general shuffles use).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xf, 0xf,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_double(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same bits in every
+// lane: within each row of 16 lanes, exchanges with lane ^ 1, lane ^ 2 (quad
+// permutations), the mirrored lane of the half-row and of the row -- each
+// step adds two partial sums that are the same in every lane that holds them
+// (x + y = y + x exactly) -- then the four row sums in fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_double(v, 0) + lane_double(v, 16)) + (lane_double(v, 32) + lane_double(v, 48));
 }
 
 // Sum K values over the block; the result is valid in thread 0.
