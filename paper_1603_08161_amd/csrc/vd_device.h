@@ -33,12 +33,17 @@ struct Tile {
 // block partials and 1.95x instead of 2.34x halo reads), wide (128-byte rows
 // along x, 4x fewer block partials, 4 nodes per thread), wide with one node
 // per thread (the wide tile on 1024 threads: its halo rows cover about half
-// as many cache lines per wave load as the small tile's).
+// as many cache lines per wave load as the small tile's), and two tall tiles
+// on 1024 threads (16 nodes along z: 1.76x / 1.90x halo reads, and an
+// observed surface facing the camera crosses fewer of their nodes, which
+// bounds the data-block work of the busiest workgroup).
 using TileS = Tile<8, 8, 4>;
 using TileM = Tile<8, 8, 8>;
 using TileW = Tile<32, 8, 4>;
 using TileX = Tile<32, 8, 4, 1024>;
-constexpr int kTileKinds = 4;
+using TileZ = Tile<8, 8, 16, 1024>;
+using TileY = Tile<16, 4, 16, 1024>;
+constexpr int kTileKinds = 6;
 
 // Maps the hardware workgroup id to a logical tile id so that each XCD gets a
 // contiguous range of tiles (neighbouring tiles then share that XCD's L2).
