@@ -64,15 +64,26 @@ __device__ __forceinline__ int energy_blocks_dev(const LevelView<T>& L) {
   return L.rblocks + (L.N + kBlock - 1) / kBlock;
 }
 
-// Block sums of K values written to out[k * stride + local].
+// Block sums of K values written to out[k * stride + local]: wave sums, then
+// thread k adds the waves' k-th sums in wave order and stores the result.
 template <int K, int NT = kBlock>
 __device__ __forceinline__ void write_partials(double (&v)[K], double* out, int stride,
                                                int local) {
-  __shared__ double lds[K * (NT / kWave)];
-  block_sum<K, NT>(v, lds);
-  if (threadIdx.x == 0) {
+  constexpr int NW = NT / kWave;
+  __shared__ double lds[K * NW];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[(size_t)k * stride + local] = v[k];
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k * NW + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += lds[threadIdx.x * NW + w];
+    out[(size_t)threadIdx.x * stride + local] = s;
   }
 }
 
