@@ -54,7 +54,7 @@ def kernel_source_sha() -> str:
 
 def measured_traffic(tile: int, name: str = "traffic_k_cg_frame64.md"):
     """HBM bytes per launch of the 64^3 CG-iteration kernel with stencil tile
-    `tile` (1..6) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    `tile` (1..7) from the committed rocprofv3 counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by the same counters on a plain copy), or None if the
     summary is missing, has no entry for that tile, or the kernel's sources
     changed since the counters were taken."""
@@ -153,7 +153,7 @@ def main() -> int:
     lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent, profile=True)
     lat.set_constraints(*inputs)
     tiles, tile_us = lat.tune(iters=10)
-    print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024]: "
+    print(f"# tiles per level {tiles}; us per CG iteration [8x8x4, 8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024, 16x4x8/512]: "
           + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us), flush=True)
 
     def step():

@@ -98,7 +98,7 @@ extern "C" {
                                          VD_FLAG_PERSIST) */
 
 #define VD_MAX_LEVELS 4
-#define VD_TILE_KINDS 6
+#define VD_TILE_KINDS 7
 #define VD_MAX_TRACE 512
 
 typedef struct vd_lattice vd_lattice;
@@ -125,8 +125,9 @@ typedef struct {
                                        default, 1 = 8x8x4, 2 = 8x8x8,
                                        3 = 32x8x4 (256 threads), 4 = 32x8x4
                                        (1024 threads), 5 = 8x8x16 (1024
-                                       threads), 6 = 16x4x16 (1024 threads)
-                                       (see vd_tune) */
+                                       threads), 6 = 16x4x16 (1024 threads),
+                                       7 = 16x4x8 (512 threads) (see
+                                       vd_tune) */
 } vd_lattice_desc;
 
 /* Correspondences of one frame (Sec. 5, used by eqs. (2)-(3)).
@@ -273,7 +274,7 @@ const char* vd_strerror(int code);
  * LDS).  For every level it times `iters` CG iterations with each tile kind
  * on the current constraints (the state is saved and restored; one warm-up
  * pass, then the fastest of three timed passes), keeps the
- * fastest for later frames and reports it in tile_out[level] (1..6, as in
+ * fastest for later frames and reports it in tile_out[level] (1..7, as in
  * vd_lattice_desc.tile) with the mean microseconds per CG iteration of each
  * kind in us_out[VD_TILE_KINDS * level + kind - 1] (either pointer may be
  * NULL).

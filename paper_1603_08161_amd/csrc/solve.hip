@@ -103,6 +103,7 @@ int tile_blocks(int kind, int nx, int ny, int nz) {
     case 3: return nb(TileX::TX, TileX::TY, TileX::TZ);
     case 4: return nb(TileZ::TX, TileZ::TY, TileZ::TZ);
     case 5: return nb(TileY::TX, TileY::TY, TileY::TZ);
+    case 6: return nb(TileH::TX, TileH::TY, TileH::TZ);
     default: return nb(TileS::TX, TileS::TY, TileS::TZ);
   }
 }
@@ -392,6 +393,7 @@ hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, 
     case 3: launch_stencil_t<T, TileX>(mode, D, pin, out, s); break;
     case 4: launch_stencil_t<T, TileZ>(mode, D, pin, out, s); break;
     case 5: launch_stencil_t<T, TileY>(mode, D, pin, out, s); break;
+    case 6: launch_stencil_t<T, TileH>(mode, D, pin, out, s); break;
     default: launch_stencil_t<T, TileS>(mode, D, pin, out, s); break;
   }
   return hipGetLastError();
@@ -711,6 +713,7 @@ hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s) {
     case 3: launch_cg_t<T, TileX>(m, D, s); break;
     case 4: launch_cg_t<T, TileZ>(m, D, s); break;
     case 5: launch_cg_t<T, TileY>(m, D, s); break;
+    case 6: launch_cg_t<T, TileH>(m, D, s); break;
     default: launch_cg_t<T, TileS>(m, D, s); break;
   }
   return hipGetLastError();
@@ -734,6 +737,7 @@ hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s) {
     case 3: k_cg_loop<T, TileX><<<D.blocks, TileX::NT, 0, s>>>(D, iters); break;
     case 4: k_cg_loop<T, TileZ><<<D.blocks, TileZ::NT, 0, s>>>(D, iters); break;
     case 5: k_cg_loop<T, TileY><<<D.blocks, TileY::NT, 0, s>>>(D, iters); break;
+    case 6: k_cg_loop<T, TileH><<<D.blocks, TileH::NT, 0, s>>>(D, iters); break;
     default: k_cg_loop<T, TileS><<<D.blocks, TileS::NT, 0, s>>>(D, iters); break;
   }
   return hipGetLastError();

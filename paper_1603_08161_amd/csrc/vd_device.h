@@ -36,14 +36,17 @@ struct Tile {
 // as many cache lines per wave load as the small tile's), and two tall tiles
 // on 1024 threads (16 nodes along z: 1.76x / 1.90x halo reads, and an
 // observed surface facing the camera crosses fewer of their nodes, which
-// bounds the data-block work of the busiest workgroup).
+// bounds the data-block work of the busiest workgroup), and the half-height
+// tall tile on 512 threads (two workgroups per CU share a CU's memory
+// bandwidth, so a tile heavy in data blocks is paired with an ordinary one).
 using TileS = Tile<8, 8, 4>;
 using TileM = Tile<8, 8, 8>;
 using TileW = Tile<32, 8, 4>;
 using TileX = Tile<32, 8, 4, 1024>;
 using TileZ = Tile<8, 8, 16, 1024>;
 using TileY = Tile<16, 4, 16, 1024>;
-constexpr int kTileKinds = 6;
+using TileH = Tile<16, 4, 8, 512>;
+constexpr int kTileKinds = 7;
 
 // Maps the hardware workgroup id to a logical tile id so that each XCD gets a
 // contiguous range of tiles (neighbouring tiles then share that XCD's L2).

@@ -22,7 +22,7 @@ def _scenes(gn=3, pcg=8):
             for k, (n, v, s) in enumerate(SIZES)]
 
 
-@pytest.mark.parametrize("tile", [1, 2, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 4, 5, 7])
 def test_batch_equals_individual_solves(tile):
     from paper_1603_08161_amd import Batch
     scenes = _scenes()

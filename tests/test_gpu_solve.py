@@ -179,7 +179,7 @@ def test_empty_constraints():
     assert rep["energy"][0] == 0.0
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
 def test_every_tile_kind_matches_replica(tile):
     scene = make_tiny(seed=7, dims=(37, 21, 18), num_levels=3, gn=3, pcg=8, n_dense=1500,
                       n_sparse=30, spacing=0.5, origin=(0.0, 0.0, 0.0))
@@ -191,7 +191,7 @@ def test_autotuner_keeps_parity():
     ref = oracle.solve_frame(scene)
     lat = make_lattice(scene, graph=True)
     tiles, us = lat.tune(iters=5)
-    assert len(tiles) == 1 and 1 <= tiles[0] <= 6
+    assert len(tiles) == 1 and 1 <= tiles[0] <= 7
     assert all(u > 0 for u in us[0])
     rep = lat.solve_frame(report=True)
     assert abs(rep["energy"][0] / ref["energy"][0] - 1.0) < 1e-4
