@@ -217,83 +217,97 @@ hipError_t launch_segments(const LevelView<T>& L, const RowView<T>& R, const uns
   return hipGetLastError();
 }
 
-// B^T B and B^T b cached per active cell (Sec. 7.1: "pre-compute and cache").
+// B^T B and B^T b cached per active cell (the per-voxel cache of Sec. 7.1).
 // Block for corners (a, b): sum over the cell's rows of
 // alpha_a alpha_b sn sn^T (symmetric 3x3); rhs block of corner a:
-// sum alpha_a sn rho.  One workgroup per cell; rows are staged through LDS
-// in chunks of 256 (corner weights computed once per row); each thread owns
-// one output entry and accumulates it in float64 over the rows in sorted
-// order (deterministic).
+// sum alpha_a sn rho.  One workgroup per cell; rows are staged through LDS in
+// chunks of 256 as the float64 products u[3a + i] = alpha_a sn_i and rho (a
+// product of two floats is exact in float64, so u_ai u_bj is the same number
+// as (alpha_a alpha_b)(sn_i sn_j)); each thread owns one output entry and
+// accumulates it in float64 over the rows in sorted order (deterministic).
+// While a chunk is accumulated, the next chunk's rows and the row indices of
+// the one after are already being loaded (cells of coarse levels hold
+// thousands of rows).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_build_cells(RowView<T> R, T* K, const Scalars* sc) {
   constexpr int P = kBlock + 1;  // padded rows: conflict-free column reads
-  __shared__ T s_w[8 * P];
-  __shared__ T s_sn[3 * P];
-  __shared__ T s_rho[kBlock];
+  __shared__ double s_u[25 * P];  // 24 products alpha_a sn_i, then rho
   const int n_active = sc->n_active;
   const int rows = R.rows;
   const int j = threadIdx.x;
-  int ca = 0, cb = 0, ci = 0, cj = 0, kind = 2;
+  int ka = 0, kb = 0, ca = 0, ci = 0, kind = 2;
   if (j < 216) {
     const int p = j / 6, comp = j % 6;
     ca = c_pair_a[p];
-    cb = c_pair_b[p];
     ci = c_comp_i[comp];
-    cj = c_comp_j[comp];
+    ka = ca * 3 + ci;
+    kb = c_pair_b[p] * 3 + c_comp_j[comp];
     kind = 0;
   } else if (j < 240) {
     ca = (j - 216) / 3;
     ci = (j - 216) % 3;
+    ka = ca * 3 + ci;
+    kb = 24;
     kind = 1;
   }
   for (int a = blockIdx.x; a < n_active; a += gridDim.x) {
     const int s0 = R.seg_start[a], s1 = R.seg_start[a + 1];
+    // row of this thread in the chunk being staged (f, sn, rho) and the row
+    // index of the following chunk
+    int row_next = (s0 + kBlock + j < s1) ? R.sorted[s0 + kBlock + j] : 0;
+    T f3[3] = {T(0), T(0), T(0)}, n3[3] = {T(0), T(0), T(0)}, rho = T(0);
+    if (s0 + j < s1) {
+      const int row = R.sorted[s0 + j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        f3[k] = R.f[(size_t)k * rows + row];
+        n3[k] = R.sn[(size_t)k * rows + row];
+      }
+      rho = R.rho[row];
+    }
     double acc = 0.0;
     for (int base = s0; base < s1; base += kBlock) {
       const int cnt = min(kBlock, s1 - base);
-      __syncthreads();
+      __syncthreads();  // the previous chunk's reads are done
       if (j < cnt) {
-        const int row = R.sorted[base + j];
-        const T fx = R.f[row], fy = R.f[(size_t)rows + row], fz = R.f[2 * (size_t)rows + row];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s_w[k * P + j] = corner_weight<T>(k, fx, fy, fz);
+        for (int c = 0; c < 8; ++c) {
+          const double w = (double)corner_weight<T>(c, f3[0], f3[1], f3[2]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s_sn[k * P + j] = R.sn[(size_t)k * rows + row];
-        s_rho[j] = R.rho[row];
+          for (int k = 0; k < 3; ++k) s_u[(c * 3 + k) * P + j] = w * (double)n3[k];
+        }
+        s_u[24 * P + j] = (double)rho;
       }
       __syncthreads();
+      // next chunk's rows (index loaded one chunk ago), and the index after
+      if (base + kBlock + j < s1) {
+        const int row = row_next;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          f3[k] = R.f[(size_t)k * rows + row];
+          n3[k] = R.sn[(size_t)k * rows + row];
+        }
+        rho = R.rho[row];
+      }
+      row_next = (base + 2 * kBlock + j < s1) ? R.sorted[base + 2 * kBlock + j] : 0;
       // four independent accumulators keep several LDS reads in flight
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      if (kind == 0) {
-        auto term = [&](int q) {
-          return (double)s_w[ca * P + q] * (double)s_w[cb * P + q] *
-                 ((double)s_sn[ci * P + q] * (double)s_sn[cj * P + q]);
-        };
+      if (kind < 2) {
+        const double* __restrict__ ua = s_u + ka * P;
+        const double* __restrict__ ub = s_u + kb * P;
         int q = 0;
         for (; q + 4 <= cnt; q += 4) {
-          a0 += term(q);
-          a1 += term(q + 1);
-          a2 += term(q + 2);
-          a3 += term(q + 3);
+          a0 += ua[q] * ub[q];
+          a1 += ua[q + 1] * ub[q + 1];
+          a2 += ua[q + 2] * ub[q + 2];
+          a3 += ua[q + 3] * ub[q + 3];
         }
-        for (; q < cnt; ++q) a0 += term(q);
-      } else if (kind == 1) {
-        auto term = [&](int q) {
-          return (double)s_w[ca * P + q] * ((double)s_sn[ci * P + q] * (double)s_rho[q]);
-        };
-        int q = 0;
-        for (; q + 4 <= cnt; q += 4) {
-          a0 += term(q);
-          a1 += term(q + 1);
-          a2 += term(q + 2);
-          a3 += term(q + 3);
-        }
-        for (; q < cnt; ++q) a0 += term(q);
+        for (; q < cnt; ++q) a0 += ua[q] * ub[q];
       }
       acc += (a0 + a1) + (a2 + a3);
     }
     if (kind == 0) {
-      const int comp = j % 6;
+      const int comp = j % 6, cb = c_pair_b[j / 6];
       K[((size_t)a * 64 + ca * 8 + cb) * 6 + comp] = (T)acc;
       if (ca != cb) K[((size_t)a * 64 + cb * 8 + ca) * 6 + comp] = (T)acc;
     } else if (kind == 1) {
