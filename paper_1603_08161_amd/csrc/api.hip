@@ -126,9 +126,8 @@ struct LevelData {
   T *d = nullptr, *r = nullptr, *r2 = nullptr, *pa = nullptr, *pb = nullptr, *ap = nullptr,
     *ap2 = nullptr, *dinv = nullptr, *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
-  int* node_slot = nullptr;  // node -> row of A27 (-1: no data term)
-  T* A27 = nullptr;          // [27*6][N] data blocks of A, per node slot
-  T* A27r = nullptr;         // [N][kA27Row] the same blocks as contiguous rows
+  int* node_slot = nullptr;  // node -> row of A27r (-1: no data term)
+  T* A27r = nullptr;         // [N][kA27Row] 27-point data blocks of A, per node slot
   Scalars* sc = nullptr;
   double* scg[2] = {nullptr, nullptr};  // CG block partials [4][max_tiles], alternating
   double* pe = nullptr;                 // energy block partials [3][energy blocks]
@@ -151,7 +150,7 @@ struct LevelData {
     v.d = d; v.r = r; v.r2 = r2; v.pa = pa; v.pb = pb; v.ap = ap; v.ap2 = ap2;
     v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
     v.scg0 = scg[0]; v.scg1 = scg[1]; v.pe = pe;
-    v.cell_map = cell_map; v.K = K; v.node_slot = node_slot; v.A27 = A27; v.A27r = A27r; v.capA = N;
+    v.cell_map = cell_map; v.K = K; v.node_slot = node_slot; v.A27r = A27r;
     v.row_cell = row_cell; v.row_f = row_f; v.row_sn = row_sn; v.row_rho = row_rho;
     v.sc = sc;
     return v;
@@ -256,7 +255,6 @@ class Solver final : public ISolver {
       VD_CHECK(pool_.alloc(&v.rot, 9 * N));
       VD_CHECK(pool_.alloc(&v.cell_map, (size_t)v.ncell));
       VD_CHECK(pool_.alloc(&v.node_slot, N));
-      VD_CHECK(pool_.alloc(&v.A27, 162 * N));
       VD_CHECK(pool_.alloc(&v.A27r, (size_t)kA27Row * N));
       VD_CHECK(pool_.alloc(&v.sc, 1));
       VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
@@ -331,8 +329,8 @@ class Solver final : public ISolver {
       VD_TRY(launch_build_cells<T>(V, R, v.K, std::min(v.cap_cells, 8192), stream_));
       VD_TRY(launch_node_flags<T>(V, node_flags_, stream_));
       VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, node_flags_, node_scan_, v.N, stream_));
-      VD_TRY(launch_assemble_nodes<T>(V, R, node_flags_, node_scan_, v.node_slot, v.A27,
-                                      v.A27r, stream_));
+      VD_TRY(launch_assemble_nodes<T>(V, R, node_flags_, node_scan_, v.node_slot, v.A27r,
+                                      stream_));
       VD_TRY(launch_set_counts(v.sc, rows, C, stream_));
     }
     rows_ = rows;

@@ -348,15 +348,14 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
 // Per node: the data part of row i of A as a 27-point block stencil,
 // A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
 // = corner b, delta = b - a) of K_c[a][b]; stored at the node's compact slot
-// both SoA [27*6][capA] (lanes holding consecutive slots read coalesced) and
 // as a row A27r[slot][kA27Row] in three 16-byte-aligned parts by dz (one part
-// is one lane's share of the node in the CG iteration).  Also the Jacobi
-// diagonal 2 w_r |N_i| + diag(A27[0]), and the data right-hand side b_i
-// gathered from the cells.
+// is one lane's share of the node in the stencil and CG kernels).  Also the
+// Jacobi diagonal 2 w_r |N_i| + diag(A27[0]), and the data right-hand side
+// b_i gathered from the cells.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowView<T> R,
                                                            const int* flags, const int* scan,
-                                                           int* node_slot, T* A27, T* A27r) {
+                                                           int* node_slot, T* A27r) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.N) return;
   const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
@@ -396,15 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
       b[1] += bc[1];
       b[2] += bc[2];
     }
-    const size_t cap = L.capA;
     T* __restrict__ row_out = A27r + (size_t)slot * kA27Row;
 #pragma unroll
     for (int dl = 0; dl < 27; ++dl)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        A27[(size_t)(dl * 6 + k) * cap + slot] = acc[dl][k];
-        row_out[(dl / 9) * kA27Part + (dl % 9) * 6 + k] = acc[dl][k];
-      }
+      for (int k = 0; k < 6; ++k) row_out[(dl / 9) * kA27Part + (dl % 9) * 6 + k] = acc[dl][k];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
@@ -424,10 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
 
 template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
-                                 const int* scan, int* node_slot, T* A27, T* A27r,
-                                 hipStream_t s) {
-  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R, flags, scan, node_slot, A27,
-                                                          A27r);
+                                 const int* scan, int* node_slot, T* A27r, hipStream_t s) {
+  k_assemble_nodes<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, R, flags, scan, node_slot, A27r);
   return hipGetLastError();
 }
 
@@ -601,7 +594,7 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_build_cells<T>(const LevelView<T>&, const RowView<T>&, T*, int,    \
                                             hipStream_t);                                       \
   template hipError_t launch_assemble_nodes<T>(const LevelView<T>&, const RowView<T>&,          \
-                                               const int*, const int*, int*, T*, T*,         \
+                                               const int*, const int*, int*, T*,             \
                                                hipStream_t);                                    \
   template hipError_t launch_node_flags<T>(const LevelView<T>&, int*, hipStream_t);             \
   template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \

@@ -142,13 +142,12 @@ struct TilePos {
 // (all 27 stencil neighbours of a tile node are in it; nodes outside the
 // lattice hold 0 and have zero blocks).
 
-// A p at own node c (tile-local) / i (global) from the tile's p in LDS:
-// the ARAP Laplacian plus the node's 27-point data blocks at A27 slot `slot`
-// (-1: no data term touches the node, or the caller adds it).
+// ARAP part of A p at own node c (tile-local) / i (global) from the tile's p
+// in LDS: 2 w_r times the 6-neighbour Laplacian.  The data part is added by
+// the caller (eval_data_nodes).
 template <typename T, typename TL>
-__device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
-                                         int gx, int gy, int gz, int slot, T& o0, T& o1,
-                                         T& o2) {
+__device__ __forceinline__ void arap_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
+                                        int gx, int gy, int gz, T& o0, T& o1, T& o2) {
   const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
   T l0 = T(0), l1 = T(0), l2 = T(0);
   const int off[3] = {1, TL::HX, TL::HX * TL::HY};
@@ -173,26 +172,10 @@ __device__ __forceinline__ void apply_at(const LevelView<T>& L, const T (*sp)[TL
   o0 = w2 * l0;
   o1 = w2 * l1;
   o2 = w2 * l2;
-  if (slot >= 0) {
-    const size_t cap = L.capA;
-    const T* __restrict__ A = L.A27 + slot;
-#pragma unroll
-    for (int dl = 0; dl < 27; ++dl) {
-      const int ddx = dl % 3 - 1, ddy = (dl / 3) % 3 - 1, ddz = dl / 9 - 1;
-      const int q = c + ddx + TL::HX * (ddy + TL::HY * ddz);
-      const T* __restrict__ blk = A + (size_t)dl * 6 * cap;
-      const T s0 = blk[0], s1 = blk[cap], s2 = blk[2 * cap], s3 = blk[3 * cap],
-              s4 = blk[4 * cap], s5 = blk[5 * cap];
-      const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
-      o0 += s0 * q0 + s1 * q1 + s2 * q2;
-      o1 += s1 * q0 + s3 * q1 + s4 * q2;
-      o2 += s2 * q0 + s4 * q1 + s5 * q2;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
-// data part of A p in the CG iteration, shared by the workgroup
+// data part of A p, shared by the workgroup (CG iteration and gradient pass)
 // ---------------------------------------------------------------------------
 //
 // Only nodes near the observed surface carry data blocks, and they cluster in
@@ -297,6 +280,7 @@ template <typename T, typename TL, int MODE>
 __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
                                                     T* __restrict__ out) {
   __shared__ T sp[3][TL::HALO];
+  __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
@@ -304,6 +288,17 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
   const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
   // the CG solve that follows a gradient pass counts its grid barrier from 0
   if (MODE == kModeRhs && w.local == 0 && threadIdx.x == 0) L.sc->bar = 0u;
+  // own nodes' data-block slots (loaded with the tile)
+  int own_slot[TL::NPT];
+#pragma unroll
+  for (int kk = 0; kk < TL::NPT; ++kk) {
+    const int c = TilePos<TL>::own(kk);
+    const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+    const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+    own_slot[kk] = in_box(gx, gy, gz, L.nx, L.ny, L.nz)
+                       ? L.node_slot[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)]
+                       : -1;
+  }
   for (int k = threadIdx.x; k < TL::HALO; k += TL::NT) {
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
@@ -318,6 +313,10 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     sp[1][k] = v1;
     sp[2][k] = v2;
   }
+  int rank[TL::NPT];
+  list_data_nodes<T, TL>(own_slot, ds, rank);
+  __syncthreads();
+  eval_data_nodes<T, TL>(L, sp, ds);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < TL::NPT; ++kk) {
@@ -327,7 +326,13 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o0, o1, o2;
-    apply_at<T, TL>(L, sp, c, gx, gy, gz, L.node_slot[i], o0, o1, o2);
+    arap_at<T, TL>(L, sp, c, gx, gy, gz, o0, o1, o2);
+    if (rank[kk] >= 0) {
+      const int e = (threadIdx.x / kWave) * DataShare<T, TL>::SEG + rank[kk];
+      o0 += ds.d[0][e];
+      o1 += ds.d[1][e];
+      o2 += ds.d[2][e];
+    }
     if (MODE == kModeApply) {
       out[i] = o0;
       out[N + i] = o1;
@@ -565,7 +570,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
-    apply_at<T, TL>(L, sp, c, gx, gy, gz, -1, o[0], o[1], o[2]);
+    arap_at<T, TL>(L, sp, c, gx, gy, gz, o[0], o[1], o[2]);
     const int e = (threadIdx.x / kWave) * DataShare<T, TL>::SEG + rank[kk];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -67,10 +67,9 @@ struct LevelView {
   // constraint cache
   const int* cell_map;  // (nx-1)(ny-1)(nz-1) -> active cell index or -1
   const T* K;           // [active][8 corners a][8 corners b][6] sym 3x3 blocks
-  const int* node_slot; // node -> slot in A27, -1 if no data term touches it
-  const T* A27;         // [27 offsets * 6][capA] data blocks of each node's row of A
-  const T* A27r;        // the same blocks as rows [capA][kA27Row] (three parts by dz)
-  int capA;             // slots allocated in A27
+  const int* node_slot; // node -> row of A27r, -1 if no data term touches it
+  const T* A27r;        // [N][kA27Row] 27-point data blocks of each node's row of A
+                        // (three parts by dz)
   // constraint rows of the current frame (SoA with stride sc->rows)
   const int* row_cell;
   const T* row_f;
@@ -139,7 +138,7 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s);
 
 template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
-                                 const int* scan, int* node_slot, T* A27, T* A27r,
+                                 const int* scan, int* node_slot, T* A27r,
                                  hipStream_t s);
 
 // ---- solve (solve.hip) ------------------------------------------------------
