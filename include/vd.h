@@ -271,13 +271,14 @@ int vd_level_info(const vd_lattice* l, int32_t level, int32_t dims[3], double* s
 const char* vd_strerror(int code);
 
 /* Autotuner of the stencil tile shape (the brick each workgroup stages in
- * LDS).  For every level it times `iters` CG iterations with each tile kind
- * on the current constraints (the state is saved and restored; one warm-up
- * pass, then the fastest of three timed passes), keeps the
- * fastest for later frames and reports it in tile_out[level] (1..7, as in
- * vd_lattice_desc.tile) with the mean microseconds per CG iteration of each
- * kind in us_out[VD_TILE_KINDS * level + kind - 1] (either pointer may be
- * NULL).
+ * LDS).  For every level it times a position step -- the gradient pass and
+ * `iters` CG iterations -- with each tile kind on the current constraints
+ * (the state is saved and restored; one warm-up pass, then the fastest of
+ * three timed passes), keeps the fastest for later frames and reports it in
+ * tile_out[level] (1..7, as in vd_lattice_desc.tile) with the step's time
+ * divided by `iters` (microseconds per CG iteration, the gradient pass
+ * included) of each kind in us_out[VD_TILE_KINDS * level + kind - 1]
+ * (either pointer may be NULL).
  * VD_ESTATE if no constraints were set.  Synchronous. */
 int vd_tune(vd_lattice* l, int32_t iters, int32_t* tile_out, double* us_out);
 

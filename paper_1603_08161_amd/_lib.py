@@ -368,8 +368,8 @@ class Lattice:
                 {PROF_NAMES[k]: int(n[k]) for k in range(len(PROF_NAMES)) if n[k] > 0})
 
     def tune(self, iters: int = 10):
-        """Run the library's tile autotuner; returns (tiles per level, mean us per
-        CG iteration [level][kind])."""
+        """Run the library's tile autotuner; returns (tiles per level, us per CG
+        iteration with the gradient pass included [level][kind])."""
         tiles = (C.c_int32 * VD_MAX_LEVELS)()
         us = (C.c_double * (VD_TILE_KINDS * VD_MAX_LEVELS))()
         _check(_lib.vd_tune(self._h, int(iters), tiles, us), "vd_tune")

@@ -672,8 +672,10 @@ class Solver final : public ISolver {
         for (int rep = 0; rep < 4; ++rep) {
           float ms = 0.0f;
           VD_TRY(hipMemcpyAsync(v.d, saved, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
-          VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, stream_));
+          // one position step: the gradient pass (which uses the same tile)
+          // and `iters` CG iterations
           VD_TRY(hipEventRecord(e0, stream_));
+          VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, stream_));
           for (int m = 0; m < iters; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), stream_));
           VD_TRY(hipEventRecord(e1, stream_));
           VD_TRY(hipEventSynchronize(e1));
