@@ -438,9 +438,10 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& 
 
 // One CG iteration m on the tile of workgroup w (body of k_cg and of the
 // persistent k_cg_loop).
-// PF: load the own nodes' slot, preconditioner, displacement and previous
-// direction together with the halo (shorter dependent chain, more registers)
-// instead of at their use.
+// PF: load the own nodes' preconditioner, displacement and previous direction
+// together with the halo (shorter dependent chain, more registers) instead of
+// at their use.  The data-block slots are loaded early in both forms: the
+// workgroup's list of data nodes needs them before the tile is staged.
 template <typename T, typename TL, bool FIRST, bool PF = true>
 __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
                                         T (&sr)[3][TL::HALO], DataShare<T, TL>& ds) {

@@ -186,6 +186,17 @@ def test_every_tile_kind_matches_replica(tile):
     _check_against_oracle(scene, {"tiles": (tile, tile, tile)})
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+def test_every_node_with_data_blocks(tile):
+    """Samples in every cell, so every node carries data blocks: each tile's
+    data-block work takes several rounds of its workgroup (4 to 13 by tile
+    kind), and nodes near tile faces read rows whose neighbours sit in the
+    halo."""
+    scene = make_tiny(seed=11, dims=(24, 20, 16), num_levels=1, gn=3, pcg=8, n_dense=20000,
+                      n_sparse=40, spacing=0.5, origin=(0.3, 0.1, -0.2))
+    _check_against_oracle(scene, {"tiles": (tile,)})
+
+
 def test_autotuner_keeps_parity():
     scene = make_config0(6)
     ref = oracle.solve_frame(scene)
