@@ -197,6 +197,16 @@ def test_every_node_with_data_blocks(tile):
     _check_against_oracle(scene, {"tiles": (tile,)})
 
 
+@pytest.mark.parametrize("tile", [1, 4, 6, 7])
+def test_fp64_tile_kinds(tile):
+    """The all-float64 mode on the larger tiles (their LDS doubles) and on a
+    lattice whose every node carries data blocks."""
+    scene = make_tiny(seed=12, dims=(24, 20, 16), num_levels=2, gn=2, pcg=8, n_dense=20000,
+                      n_sparse=40, spacing=0.5, origin=(0.3, 0.1, -0.2))
+    _check_against_oracle(scene, {"tiles": (tile, tile), "precision": "fp64"}, e_tol=1e-9,
+                          x_tol=1e-5)
+
+
 def test_autotuner_keeps_parity():
     scene = make_config0(6)
     ref = oracle.solve_frame(scene)
