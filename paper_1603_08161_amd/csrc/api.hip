@@ -265,7 +265,7 @@ class Solver final : public ISolver {
       VD_CHECK(ensure_partials(v, 0));
     }
     if ((desc_.flags & VD_FLAG_PROFILE) && (desc_.flags & VD_FLAG_GRAPH))
-      VD_CHECK(pool_.alloc(&stamps_, 2 * kMaxStamped));  // written by captured stamp kernels
+      VD_CHECK(pool_.alloc(&stamps_, 2 * kMaxStamped));  // written by captured CG launches
     VD_CHECK(pool_.alloc(&node_flags_, (size_t)finest().N));
     VD_CHECK(pool_.alloc(&node_scan_, (size_t)finest().N));
     VD_CHECK(pool_.alloc(&d_flags_, 4));
@@ -740,17 +740,17 @@ class Solver final : public ISolver {
           VD_CHECK(timed(on, VD_PROF_CG_LOOP, s,
                          [&] { return launch_cg_loop<T>(pcg, tiles_of(V), s); }));
         } else if (graph_prof && l == L_ - 1 && pcg > 1) {
-          // captured frame: device clock stamps (a one-thread kernel each)
-          // around the iterations after the first, written on every replay
+          // captured frame: the device clock at the start of CG iteration 1
+          // and of the final step (first workgroup of each), written on
+          // every replay, time iterations 1 .. pcg-1
           if (!stamps_) return VD_ESTATE;  // allocated at creation with both flags
           VD_TRY(launch_cg<T>(0, tiles_of(V), s));
           const int a = 2 * n_stamped_;
-          VD_TRY(launch_stamp(stamps_, a, s));
-          for (int m = 1; m < pcg; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), s));
-          VD_TRY(launch_stamp(stamps_, a + 1, s));
+          for (int m = 1; m < pcg; ++m)
+            VD_TRY(launch_cg<T>(m, tiles_of(V), s, m == 1 ? stamps_ + a : nullptr));
           if (n_stamped_ < kMaxStamped) ++n_stamped_;
           stamped_launches_ = pcg - 1;
-          VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
+          VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s, stamps_ + a + 1));
         } else {
           for (int m = 0; m < pcg; ++m)
             VD_CHECK(

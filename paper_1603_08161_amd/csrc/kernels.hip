@@ -437,15 +437,6 @@ hipError_t launch_set_counts(Scalars* sc, int rows, int n_dense, hipStream_t s) 
   return hipGetLastError();
 }
 
-__global__ void k_stamp(unsigned long long* dst, int idx) {
-  if (threadIdx.x == 0) dst[idx] = (unsigned long long)wall_clock64();
-}
-
-hipError_t launch_stamp(unsigned long long* dst, int idx, hipStream_t s) {
-  k_stamp<<<1, 64, 0, s>>>(dst, idx);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(kBlock) void k_check_finite(const float* v, int64_t n, int* flags) {
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;

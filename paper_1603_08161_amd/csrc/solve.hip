@@ -591,11 +591,18 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   write_partials<4, TL::NT>(part, s_out, w.count, w.local);
 }
 
+// Clock stamp of a launch's first workgroup at its start (graph timing).
+__device__ __forceinline__ void entry_stamp(unsigned long long* stamp) {
+  if (stamp != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+    *stamp = (unsigned long long)wall_clock64();
+}
+
 template <typename T, typename TL, bool FIRST>
-__global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m) {
+__global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m, unsigned long long* stamp) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   __shared__ DataShare<T, TL> ds;
+  entry_stamp(stamp);
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   cg_body<T, TL, FIRST>(w, m, sp, sr, ds);
 }
@@ -605,10 +612,12 @@ __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m) {
 // workgroups (batched lattices) occupancy hides more latency than the
 // register-held prefetches of k_cg.
 template <typename T, typename TL, bool FIRST>
-__global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m) {
+__global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m,
+                                                   unsigned long long* stamp) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   __shared__ DataShare<T, TL> ds;
+  entry_stamp(stamp);
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   cg_body<T, TL, FIRST, false>(w, m, sp, sr, ds);
 }
@@ -684,7 +693,9 @@ __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
 
 // d += alpha p of the last CG iterate (node workgroups).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
+__global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
+                                                     unsigned long long* stamp) {
+  entry_stamp(stamp);
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
   const bool odd = (last & 1) != 0;
@@ -700,35 +711,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last) {
 }
 
 template <typename T, typename TL>
-void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s) {
+void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s, unsigned long long* stamp) {
   if ((long)D.blocks * TL::NT > (long)kOneRoundBlocks * kBlock) {
-    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m);
-    else k_cg_occ<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m);
+    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    else k_cg_occ<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
   } else {
-    if (m == 0) k_cg<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m);
-    else k_cg<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m);
+    if (m == 0) k_cg<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    else k_cg<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
   }
 }
 
 template <typename T>
-hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s) {
+hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s, unsigned long long* stamp) {
   if (D.blocks <= 0) return hipSuccess;
   switch (D.one.tile) {
-    case 1: launch_cg_t<T, TileM>(m, D, s); break;
-    case 2: launch_cg_t<T, TileW>(m, D, s); break;
-    case 3: launch_cg_t<T, TileX>(m, D, s); break;
-    case 4: launch_cg_t<T, TileZ>(m, D, s); break;
-    case 5: launch_cg_t<T, TileY>(m, D, s); break;
-    case 6: launch_cg_t<T, TileH>(m, D, s); break;
-    default: launch_cg_t<T, TileS>(m, D, s); break;
+    case 1: launch_cg_t<T, TileM>(m, D, s, stamp); break;
+    case 2: launch_cg_t<T, TileW>(m, D, s, stamp); break;
+    case 3: launch_cg_t<T, TileX>(m, D, s, stamp); break;
+    case 4: launch_cg_t<T, TileZ>(m, D, s, stamp); break;
+    case 5: launch_cg_t<T, TileY>(m, D, s, stamp); break;
+    case 6: launch_cg_t<T, TileH>(m, D, s, stamp); break;
+    default: launch_cg_t<T, TileS>(m, D, s, stamp); break;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s) {
+hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s,
+                           unsigned long long* stamp) {
   if (D.blocks <= 0) return hipSuccess;
-  k_cg_final<T><<<D.blocks, kBlock, 0, s>>>(D, last);
+  k_cg_final<T><<<D.blocks, kBlock, 0, s>>>(D, last, stamp);
   return hipGetLastError();
 }
 
@@ -1029,8 +1041,9 @@ hipError_t launch_set_rest(const Dispatch<T>& D, hipStream_t s) {
 
 #define VD_INSTANTIATE_SOLVE(T)                                                                  \
   template hipError_t launch_stencil<T>(int, const Dispatch<T>&, const T*, T*, hipStream_t);    \
-  template hipError_t launch_cg<T>(int, const Dispatch<T>&, hipStream_t);                        \
-  template hipError_t launch_cg_final<T>(int, const Dispatch<T>&, hipStream_t);                  \
+  template hipError_t launch_cg<T>(int, const Dispatch<T>&, hipStream_t, unsigned long long*);   \
+  template hipError_t launch_cg_final<T>(int, const Dispatch<T>&, hipStream_t,                   \
+                                          unsigned long long*);                                 \
   template hipError_t launch_energy<T>(const Dispatch<T>&, const Dispatch<T>&, int, hipStream_t); \
   template hipError_t launch_reset_counters<T>(const Dispatch<T>&, hipStream_t);                 \
   template hipError_t launch_cg_loop<T>(int, const Dispatch<T>&, hipStream_t);                   \

@@ -163,12 +163,16 @@ template <typename T>
 hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s);
 
 // CG iteration m (first: m == 0) on every lattice of D (tile workgroups).
+// stamp (may be NULL): the first workgroup writes the device's constant-rate
+// wall clock there when it starts (timing inside a captured graph).
 template <typename T>
-hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s);
+hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s,
+                     unsigned long long* stamp = nullptr);
 
-// d += alpha p of CG iterate `last` (node workgroups).
+// d += alpha p of CG iterate `last` (node workgroups); stamp as launch_cg.
 template <typename T>
-hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s);
+hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s,
+                           unsigned long long* stamp = nullptr);
 
 // All `iters` CG iterations and the last step of one position solve in one
 // launch (one lattice; all its tiles resident at once, with a grid barrier
@@ -215,10 +219,6 @@ inline Dispatch<T> single(const LevelView<T>& L, int blocks) {
   D.blocks = blocks;
   return D;
 }
-
-// dst[idx] = the device's constant-rate wall clock (one thread), for timing
-// launches inside a captured graph.
-hipError_t launch_stamp(unsigned long long* dst, int idx, hipStream_t s);
 
 // flags |= 1 where any of the n floats is not finite.
 hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s);
