@@ -18,11 +18,6 @@ __device__ __forceinline__ bool in_box(int x, int y, int z, int nx, int ny, int 
   return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
 }
 
-// Row-major index of rotation entry (row, col) in the [9][N] SoA array.
-__device__ __forceinline__ size_t rot_at(int row, int col, size_t N, size_t i) {
-  return (size_t)(row * 3 + col) * N + i;
-}
-
 // Unique (a <= b) corner pairs of a cell and the six components of a
 // symmetric 3x3 block.
 __constant__ unsigned char c_pair_a[36] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2,
