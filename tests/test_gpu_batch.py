@@ -38,6 +38,22 @@ def test_batch_equals_individual_solves(tile):
         np.testing.assert_array_equal(lat.get_energy(), rep["energy"])
 
 
+@pytest.mark.parametrize("tile", [0, 7])
+def test_batch_equals_individual_solves_fp64(tile):
+    """The all-float64 mode through the batched launches (the register-lean
+    CG form at the finest level) against single-lattice solves, bitwise."""
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes(gn=2, pcg=6)[:3]
+    kw = {"precision": "fp64", "tiles": (tile, tile, tile)}
+    lats = [make_lattice(s, **kw) for s in scenes]
+    E_batch = Batch(lats).solve(reset=True, energies=True)
+    for s, lat, e in zip(scenes, lats, E_batch):
+        ref = make_lattice(s, **kw)
+        rep = ref.solve_frame(reset=True, report=True)
+        np.testing.assert_array_equal(e, rep["energy"])
+        np.testing.assert_array_equal(lat.get_state()[0], ref.get_state()[0])
+
+
 def test_batch_matches_oracle():
     from paper_1603_08161_amd import Batch
     scenes = _scenes()
