@@ -241,6 +241,24 @@ def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, gra
     assert dx < (1e-5 if precision == "fp32" else 1e-6), dx
 
 
+@pytest.mark.parametrize("tile", [4, 6, 7])
+def test_persistent_cg_loop_on_large_tiles(tile):
+    """The persistent loop with the 1024- and 512-thread tiles on a lattice
+    whose every node carries data blocks (20-40 tiles, all resident)."""
+    from paper_1603_08161_amd import VD_REPORT_BARRIER_TIMEOUT
+    scene = make_tiny(seed=13, dims=(24, 20, 16), num_levels=1, gn=2, pcg=8, n_dense=20000,
+                      n_sparse=40, spacing=0.5, origin=(0.3, 0.1, -0.2))
+    out = {}
+    for persistent in (True, False):
+        lat = make_lattice(scene, tiles=(tile,), persistent=persistent)
+        rep = lat.solve_frame(report=True)
+        assert not rep["bits"] & VD_REPORT_BARRIER_TIMEOUT
+        out[persistent] = (rep["energy"], lat.get_state()[0])
+    assert abs(out[True][0][0] / out[False][0][0] - 1.0) < 1e-6
+    dx = np.abs(out[True][1].astype(np.float64) - out[False][1]).max() / scene.spec.spacing
+    assert dx < 1e-5, dx
+
+
 def test_graph_profile_events_time_the_finest_cg_and_change_nothing():
     """With graph + profile, HIP events captured in the frame time the finest
     level's CG iterations of every replay; the solve itself is unchanged."""
