@@ -224,26 +224,70 @@ struct Fit {
 // be exercised on the CPU.
 #define VD_HD __host__ __device__ __forceinline__
 
+// Tangent t = tan(phi) and cosine c of the Jacobi rotation in the (p, q)
+// plane that annihilates a_pq, from theta = (a_qq - a_pp) / (2 a_pq) (the
+// smaller root, |phi| <= pi / 4).  Returns false when there is nothing to
+// rotate.
+template <typename T>
+VD_HD bool jacobi_tc(T app, T aqq, T apq, T& t, T& c) {
+  if (apq == T(0)) return false;
+  const T theta = (aqq - app) / (T(2) * apq);
+  const T sgn = theta >= T(0) ? T(1) : T(-1);
+  t = sgn / (fabs(theta) + sqrt(theta * theta + T(1)));
+  c = T(1) / sqrt(t * t + T(1));
+  return true;
+}
+// float32 on the GPU: the hardware reciprocal, square root and reciprocal
+// square root (about 1 ulp) replace the correctly rounded sequences.  t and c
+// then carry a few ulp of error, the rotation stays orthonormal to float32
+// precision, and the quaternion is normalised at the end of the fit anyway.
+// |a_pq| below 1e-30 is left alone (it keeps 1 / (2 a_pq) finite); beyond
+// |theta| = 1e15, where theta^2 would soon overflow, t = 1 / (2 |theta|),
+// the root to float32 precision there.
+template <>
+VD_HD bool jacobi_tc<float>(float app, float aqq, float apq, float& t, float& c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (!(fabsf(apq) >= 1e-30f)) return false;
+  const float theta = (aqq - app) * __builtin_amdgcn_rcpf(2.0f * apq);
+  const float at = fabsf(theta);
+  const float ta = at > 1e15f ? 0.5f * __builtin_amdgcn_rcpf(at)
+                              : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(at * at + 1.0f));
+  t = theta >= 0.0f ? ta : -ta;
+  c = __builtin_amdgcn_rsqf(t * t + 1.0f);
+#else
+  if (apq == 0.0f) return false;
+  const float theta = (aqq - app) / (2.0f * apq);
+  const float sgn = theta >= 0.0f ? 1.0f : -1.0f;
+  t = sgn / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
+  c = 1.0f / sqrtf(t * t + 1.0f);
+#endif
+  return true;
+}
+
+// One cyclic-Jacobi rotation A <- J^T A J, V <- V J in the (p, q) plane of the
+// symmetric A (Golub and Van Loan, the symmetric Schur decomposition).  Only
+// rows and columns p and q change: a_pp and a_qq move by -/+ t a_pq, a_pq
+// becomes exactly 0, and the other entries of the two columns rotate (their
+// mirror entries are written too, so A stays exactly symmetric).
 template <typename T>
 VD_HD void jacobi_rotate(T (&A)[4][4], T (&V)[4][4], int p, int q) {
-  const T apq = A[p][q];
-  if (apq == T(0)) return;
-  const T theta = (A[q][q] - A[p][p]) / (T(2) * apq);
-  const T sgn = theta >= T(0) ? T(1) : T(-1);
-  const T t = sgn / (fabs(theta) + sqrt(theta * theta + T(1)));
-  const T c = T(1) / sqrt(t * t + T(1));
+  T t, c;
+  if (!jacobi_tc(A[p][p], A[q][q], A[p][q], t, c)) return;
   const T s = t * c;
+  const T tap = t * A[p][q];
+  A[p][p] -= tap;
+  A[q][q] += tap;
+  A[p][q] = T(0);
+  A[q][p] = T(0);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const T akp = A[k][p], akq = A[k][q];
-    A[k][p] = c * akp - s * akq;
-    A[k][q] = s * akp + c * akq;
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const T apk = A[p][k], aqk = A[q][k];
-    A[p][k] = c * apk - s * aqk;
-    A[q][k] = s * apk + c * aqk;
+  for (int r = 0; r < 4; ++r) {
+    if (r == p || r == q) continue;
+    const T arp = A[r][p], arq = A[r][q];
+    const T np = c * arp - s * arq, nq = s * arp + c * arq;
+    A[r][p] = np;
+    A[p][r] = np;
+    A[r][q] = nq;
+    A[q][r] = nq;
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
