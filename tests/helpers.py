@@ -61,3 +61,27 @@ def make_lattice(scene, **kw):
 
 def oracle_solve(scene, **kw):
     return oracle.solve_frame(scene, **kw)
+
+
+def edge_fit_cases(seed, n=600):
+    """Cross-covariances (float32-representable, as float64) that drive the
+    rotation fit's Jacobi sweeps to their edge branches, with previous
+    rotations: a third nearly diagonal (distinct diagonal magnitudes about
+    3, 2, 1 with random signs, off-diagonal entries 1e-6 down to 1e-33 of the
+    diagonal: tiny rotation angles, |theta| far beyond 1e15, entries too small
+    to rotate), a third random scaled by 1e-15 and a third by 1e15.  The
+    previous rotation is the identity for even cases and a half turn about z
+    for odd ones (a different basis of the warm start)."""
+    rng = np.random.default_rng(seed)
+    k = n // 3
+    M = np.empty((n, 3, 3))
+    mag = np.array([3.0, 2.0, 1.0]) * (1.0 + 0.1 * rng.uniform(-1, 1, size=(k, 3)))
+    mag = np.take_along_axis(mag, np.argsort(rng.uniform(size=(k, 3)), axis=1), axis=1)
+    diag = mag * rng.choice([-1.0, 1.0], size=(k, 3))
+    rel = 10.0 ** rng.uniform(-33, -6, size=(k, 1, 1))
+    M[:k] = rng.normal(size=(k, 3, 3)) * rel + diag[:, :, None] * np.eye(3)
+    M[k:2 * k] = rng.normal(size=(k, 3, 3)) * 1e-15
+    M[2 * k:] = rng.normal(size=(n - 2 * k, 3, 3)) * 1e15
+    Rp = np.broadcast_to(np.eye(3), (n, 3, 3)).copy()
+    Rp[1::2] = np.diag([-1.0, -1.0, 1.0])
+    return M.astype(np.float32).astype(np.float64), Rp

@@ -14,7 +14,7 @@ import pytest
 from oracle.procrustes import fit_rotations
 from synth import random_rotation
 
-from helpers import rotation_angle
+from helpers import edge_fit_cases, rotation_angle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "native", "fit_host.cpp")
@@ -73,3 +73,16 @@ def test_fit_independent_of_warm_start(fit_exe):
     R1, _ = _run(fit_exe, M, np.broadcast_to(np.eye(3), M.shape).copy(), 1)
     R2, _ = _run(fit_exe, M, np.stack([random_rotation(rng) for _ in range(M.shape[0])]), 1)
     assert rotation_angle(R1[~deg], R2[~deg]).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-10)])
+def test_fit_edge_cases(fit_exe, prec, tol):
+    """Nearly diagonal (rotation angles down to 1e-33) and 1e-15 / 1e15-scaled
+    cross-covariances: the host build of the fit matches the oracle's SVD."""
+    M, Rp = edge_fit_cases(12)
+    R_ref, deg = fit_rotations(M, Rp)
+    assert not deg.any()
+    R, code = _run(fit_exe, M, Rp, prec)
+    assert not (code == 2).any()
+    ang = rotation_angle(R, R_ref)
+    assert ang.max() < tol, ang.max()

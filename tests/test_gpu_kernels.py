@@ -16,7 +16,8 @@ from oracle.procrustes import fit_rotations as oracle_fit, rotation_step
 from oracle.solver import LevelSystem
 from synth import make_config0, make_config1, make_tiny
 
-from helpers import grids_of, make_lattice, oracle_cons, random_state, rel_err, rotation_angle
+from helpers import (edge_fit_cases, grids_of, make_lattice, oracle_cons, random_state, rel_err,
+                     rotation_angle)
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +136,23 @@ def test_batched_fit_matches_oracle(precision):
     obj = np.einsum("nab,nab->n", R.astype(np.float64), M.astype(np.float64))
     obj_ref = np.einsum("nab,nab->n", R_ref, M.astype(np.float64))
     np.testing.assert_allclose(obj[~deg], obj_ref[~deg], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batched_fit_edge_cases(precision):
+    """Nearly diagonal cross-covariances (rotation angles down to 1e-33, where
+    the float32 sweeps take their large-theta and too-small-to-rotate
+    branches) and covariances scaled by 1e-15 and 1e15 fit the same rotation
+    as the oracle's SVD."""
+    from paper_1603_08161_amd import fit_rotations
+    M, prev = edge_fit_cases(11)
+    R_ref, deg = oracle_fit(M, prev)
+    assert not deg.any()
+    R, code = fit_rotations(M.astype(np.float32), prev.astype(np.float32), precision=precision)
+    assert np.isfinite(R).all()
+    assert not (code == 2).any()
+    ang = rotation_angle(R, R_ref)
+    assert ang.max() < (1e-5 if precision == "fp32" else 3e-7), ang.max()
 
 
 def test_prolong_matches_oracle():
