@@ -358,7 +358,10 @@ VD_HD void fit_rotation(const T (&M)[9], const T (&q0)[4], Fit<T>& out) {
                 Lq[3][r] * NL[3][c];
   T V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
   const T tol = sizeof(T) == 4 ? T(1e-14) : T(1e-30);
-#pragma unroll 1
+  // fully unrolled: A and V then stay in fixed registers across sweeps (a
+  // rolled loop copies a dozen of them per rotation, and the rotation-fit
+  // kernel needs 117 instead of 142 VGPRs)
+#pragma unroll
   for (int sweep = 0; sweep < SWEEPS; ++sweep) {
     const T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[0][3] * A[0][3] +
                   A[1][2] * A[1][2] + A[1][3] * A[1][3] + A[2][3] * A[2][3];
