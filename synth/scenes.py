@@ -63,6 +63,19 @@ class Scene:
         return int(self.sparse_canon.shape[0])
 
 
+@dataclass
+class DepthFrame:
+    """One sensor frame and the model samples a projective association starts
+    from: depth (H, W) float32 (0 = no measurement), pinhole intrinsics
+    (width, height, fx, fy, cx, cy), canonical sample positions and normals
+    (M, 3) float32."""
+
+    depth: np.ndarray
+    camera: Dict
+    model_canon: np.ndarray
+    model_normal: np.ndarray
+
+
 # ---------------------------------------------------------------------------
 # ground-truth warp used to make targets
 # ---------------------------------------------------------------------------
@@ -158,24 +171,48 @@ CFG1_MINOR = 0.10           # torus minor radius (m)
 CFG1_TILT_DEG = 30.0        # tilt of the torus axis away from the view axis
 
 
-def _torus_points(rng, n_theta, n_phi, major, minor, noise_amp):
+def _torus_points(rng, n_theta, n_phi, major, minor, noise_amp, with_normals=False):
     """Canonical torus points (local frame, axis = z) with a smooth random
-    perturbation of the tube radius (low-frequency signed-distance noise)."""
+    perturbation of the tube radius (low-frequency signed-distance noise).
+    With ``with_normals`` also the outward unit normals of that surface
+    (cross product of its parameter derivatives), drawn from the same rng
+    state, so the points are the same either way."""
     th = (np.arange(n_theta) + rng.uniform()) * (2 * np.pi / n_theta)
     ph = (np.arange(n_phi) + rng.uniform()) * (2 * np.pi / n_phi)
     T, P = np.meshgrid(th, ph, indexing="ij")
     T = T.ravel()
     P = P.ravel()
-    eta = np.zeros_like(T)
+    terms = []
     freqs = [(1, 1), (2, 1), (3, 2), (1, 2), (2, 3)]
     for (m, k) in freqs:
-        eta += rng.normal() * np.sin(m * T + k * P + rng.uniform(0, 2 * np.pi))
-    eta *= noise_amp / max(np.abs(eta).max(), 1e-12)
-    rr = minor + eta
-    x = (major + rr * np.cos(P)) * np.cos(T)
-    y = (major + rr * np.cos(P)) * np.sin(T)
-    z = rr * np.sin(P)
-    return np.stack([x, y, z], axis=1)
+        terms.append((rng.normal(), m, k, rng.uniform(0, 2 * np.pi)))
+
+    def surface(T, P):
+        eta = np.zeros_like(T)
+        for (a, m, k, ph0) in terms:
+            eta += a * np.sin(m * T + k * P + ph0)
+        return eta
+
+    eta = surface(T, P)
+    scale = noise_amp / max(np.abs(eta).max(), 1e-12)
+
+    def embed(T, P):
+        rr = minor + scale * surface(T, P)
+        return np.stack([(major + rr * np.cos(P)) * np.cos(T),
+                         (major + rr * np.cos(P)) * np.sin(T), rr * np.sin(P)], axis=1)
+
+    pts = embed(T, P)
+    if not with_normals:
+        return pts
+    d = 1e-5
+    dT = embed(T + d, P) - embed(T - d, P)
+    dP = embed(T, P + d) - embed(T, P - d)
+    nrm = np.cross(dT, dP)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    ring = np.stack([major * np.cos(T), major * np.sin(T), np.zeros_like(T)], axis=1)
+    out = np.einsum("na,na->n", nrm, pts - ring) < 0
+    nrm[out] = -nrm[out]
+    return pts, nrm
 
 
 def _rot_x(deg):
@@ -254,7 +291,13 @@ def _depth_normals(depth, cam, max_jump=0.02, min_cos=0.2):
 def make_config1(seed: int = 0, n: int = 64, num_levels: int = 3,
                  gn: int = 8, pcg: int = 20, n_sparse: int = 500,
                  n_theta: int = 2400, n_phi: int = 900,
-                 rbf_centres_override=None) -> Scene:
+                 rbf_centres_override=None, depth_frame: bool = False):
+    """The 64^3 workload.  With ``depth_frame`` also returns a
+    :class:`DepthFrame` of the same frame: the noisy depth map the dense
+    constraints were read from and the model samples a projective
+    association starts from (the canonical surface points that are visible
+    when the undeformed surface is rendered with the same camera, with their
+    outward normals)."""
     rng = np.random.default_rng(seed)
     h = CFG1_H * 64.0 / n
     coarse_span = (2 ** (num_levels - 1)) * h * (int(np.ceil(n / 2 ** (num_levels - 1))) - 1)
@@ -264,7 +307,8 @@ def make_config1(seed: int = 0, n: int = 64, num_levels: int = 3,
                        num_levels=num_levels, gn_iters=(gn,) * num_levels,
                        pcg_iters=(pcg,) * num_levels,
                        w_dense=1.0, w_sparse=10.0, w_arap=5.0)
-    local = _torus_points(rng, n_theta, n_phi, CFG1_MAJOR, CFG1_MINOR, 0.5 * CFG1_H)
+    local, local_n = _torus_points(rng, n_theta, n_phi, CFG1_MAJOR, CFG1_MINOR, 0.5 * CFG1_H,
+                                   with_normals=True)
     canon = local @ _rot_x(CFG1_TILT_DEG).T + centre[None, :]
     ext = CFG1_MAJOR + CFG1_MINOR
     if rbf_centres_override is None:
@@ -287,15 +331,26 @@ def make_config1(seed: int = 0, n: int = 64, num_levels: int = 3,
     pick = rng.choice(win.size, size=min(n_sparse, win.size), replace=False)
     sp_canon = p_hat[pick]
     sp_target = warp.apply(sp_canon) + rng.normal(scale=1e-3, size=sp_canon.shape)
-    return Scene(spec=spec,
-                 canon=p_hat.astype(np.float32), target=target.astype(np.float32),
-                 normal=normal.astype(np.float32),
-                 weight=np.ones(p_hat.shape[0], np.float32),
-                 sparse_canon=sp_canon.astype(np.float32),
-                 sparse_target=sp_target.astype(np.float32),
-                 meta={"config": 1, "seed": seed, "valid_pixels": int(p_hat.shape[0]),
-                       "rbf_centres": centres, "rbf_amps": amps,
-                       "rbf_sigma": 16.0 * CFG1_H, "camera": CAM})
+    scene = Scene(spec=spec,
+                  canon=p_hat.astype(np.float32), target=target.astype(np.float32),
+                  normal=normal.astype(np.float32),
+                  weight=np.ones(p_hat.shape[0], np.float32),
+                  sparse_canon=sp_canon.astype(np.float32),
+                  sparse_target=sp_target.astype(np.float32),
+                  meta={"config": 1, "seed": seed, "valid_pixels": int(p_hat.shape[0]),
+                        "rbf_centres": centres, "rbf_amps": amps,
+                        "rbf_sigma": 16.0 * CFG1_H, "camera": CAM})
+    if not depth_frame:
+        return scene
+    canon_n = local_n @ _rot_x(CFG1_TILT_DEG).T
+    # model samples: the undeformed surface rendered with the same camera
+    # (drawn after every other random number, so the scene is unchanged)
+    _, _, win0 = _render(canon, CAM, 0.0, rng)
+    vis = win0[win0 >= 0]
+    frame = DepthFrame(depth=noisy.astype(np.float32), camera=dict(CAM),
+                       model_canon=canon[vis].astype(np.float32),
+                       model_normal=canon_n[vis].astype(np.float32))
+    return scene, frame
 
 
 # ---------------------------------------------------------------------------
@@ -477,9 +532,104 @@ def make_config2(seed: int = 0, count: int = 32, n_range=(24, 64), valid_range=(
                  sparse_range=(100, 400)):
     """The batched workload: ``count`` lattices with node counts per axis drawn
     uniformly from ``n_range``, each with its own seeded surface and frame."""
+    ns, valid, sparse = config2_sizes(seed, count, n_range, valid_range, sparse_range)
+    return [make_batch_lattice(1000 * seed + k, int(ns[k]), int(valid[k]), int(sparse[k]))
+            for k in range(count)]
+
+
+def config2_sizes(seed: int = 0, count: int = 32, n_range=(24, 64), valid_range=(5000, 60000),
+                  sparse_range=(100, 400)):
+    """Node counts per axis, valid-pixel targets and sparse-pair counts of the
+    batched workload's lattices (the draws ``make_config2`` uses)."""
     rng = np.random.default_rng(seed)
     ns = rng.integers(n_range[0], n_range[1] + 1, size=count)
     valid = rng.integers(valid_range[0], valid_range[1] + 1, size=count)
     sparse = rng.integers(sparse_range[0], sparse_range[1] + 1, size=count)
-    return [make_batch_lattice(1000 * seed + k, int(ns[k]), int(valid[k]), int(sparse[k]))
-            for k in range(count)]
+    return ns, valid, sparse
+
+
+def make_config2_member(seed: int, k: int, count: int = 32) -> Scene:
+    """Lattice k of ``make_config2(seed, count)`` alone (the same scene)."""
+    ns, valid, sparse = config2_sizes(seed, count)
+    return make_batch_lattice(1000 * seed + k, int(ns[k]), int(valid[k]), int(sparse[k]))
+
+
+# ---------------------------------------------------------------------------
+# planar scenes with exact depth maps (association and rigid-pose checks)
+# ---------------------------------------------------------------------------
+
+def render_planes(cam: Dict, planes, dtype=np.float32) -> np.ndarray:
+    """Depth map of the inside of a convex region {x : m_k . x >= b_k} seen
+    from the camera at the origin (which must lie inside, b_k <= 0): each
+    pixel-centre ray (u + 1/2 - cx)/fx, (v + 1/2 - cy)/fy, 1) leaves the
+    region through the first plane it reaches; that distance along z is the
+    depth.  planes: list of (unit normal m (3,), offset b)."""
+    W, H = cam["width"], cam["height"]
+    uu, vv = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    d = np.stack([(uu - cam["cx"]) / cam["fx"], (vv - cam["cy"]) / cam["fy"],
+                  np.ones_like(uu)], axis=-1)
+    depth = np.full((H, W), np.inf)
+    for m, b in planes:
+        md = d @ np.asarray(m, np.float64)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            s = np.where(md < 0, b / md, np.inf)
+        depth = np.minimum(depth, s)
+    depth[~np.isfinite(depth)] = 0.0
+    return depth.astype(dtype)
+
+
+BOX_PLANES = (  # inside corner of a box, in front of the camera (metres)
+    (np.array([1.0, 0.0, 0.0]), -0.35),    # wall  x >= -0.35
+    (np.array([0.0, -1.0, 0.0]), -0.25),   # floor y <= 0.25
+    (np.array([0.0, 0.0, -1.0]), -1.10),   # back  z <= 1.10
+    (np.array([-1.0, 0.0, 0.0]), -0.60),   # wall  x <= 0.60 (keeps rays bounded)
+)
+
+
+def moved_planes(planes, Q: np.ndarray, c: np.ndarray):
+    """The planes after the rigid motion x -> Q x + c."""
+    out = []
+    for m, b in planes:
+        mq = np.asarray(Q, np.float64) @ m
+        out.append((mq, b + mq @ np.asarray(c, np.float64)))
+    return out
+
+
+def make_box_frame(Q=None, c=None, cam: Dict = CAM, step: int = 3, margin: int = 4,
+                   noise: float = 0.0, seed: int = 0) -> DepthFrame:
+    """Depth map of the box corner after the rigid motion (Q, c), with model
+    samples taken from the unmoved corner: pixel-centre points of its exact
+    depth map on a ``step``-pixel grid, at least ``margin`` pixels from any
+    crease or image border, with the plane normals facing the camera."""
+    Q = np.eye(3) if Q is None else np.asarray(Q, np.float64)
+    c = np.zeros(3) if c is None else np.asarray(c, np.float64)
+    rng = np.random.default_rng(seed)
+    depth = render_planes(cam, moved_planes(BOX_PLANES, Q, c)).astype(np.float64)
+    if noise > 0:
+        depth = np.where(depth > 0, depth + rng.normal(scale=noise, size=depth.shape), 0.0)
+    rest = render_planes(cam, BOX_PLANES).astype(np.float64)
+    W, H = cam["width"], cam["height"]
+    uu, vv = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    d = np.stack([(uu - cam["cx"]) / cam["fx"], (vv - cam["cy"]) / cam["fy"],
+                  np.ones_like(uu)], axis=-1)
+    # which plane each pixel sees, and whether its neighbourhood sees the same
+    label = np.full((H, W), -1)
+    best = np.full((H, W), np.inf)
+    for k, (m, b) in enumerate(BOX_PLANES):
+        md = d @ m
+        with np.errstate(divide="ignore", invalid="ignore"):
+            s = np.where(md < 0, b / md, np.inf)
+        upd = s < best
+        best[upd] = s[upd]
+        label[upd] = k
+    ok = np.zeros((H, W), bool)
+    ok[margin:H - margin:step, margin:W - margin:step] = True
+    for dy in range(-margin, margin + 1):
+        for dx in range(-margin, margin + 1):
+            ok &= np.roll(np.roll(label, dy, 0), dx, 1) == label
+    vv_i, uu_i = np.nonzero(ok)
+    pts = d[vv_i, uu_i] * rest[vv_i, uu_i][:, None]
+    # the inward normals m_k of the region's faces point toward the camera
+    nrm = np.stack([BOX_PLANES[k][0] for k in label[vv_i, uu_i]])
+    return DepthFrame(depth=depth.astype(np.float32), camera=dict(cam),
+                      model_canon=pts.astype(np.float32), model_normal=nrm.astype(np.float32))

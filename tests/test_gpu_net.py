@@ -284,3 +284,35 @@ def test_warm_start_judge_fp64():
     np.testing.assert_array_equal(lat.get_state()[0], pos_plain)
     with pytest.raises(Exception):
         lat.solve_frame(init_delta=np.full((3, pos0.shape[0]), np.nan, np.float32))
+
+
+def test_adam_three_steps_match_oracle_sequence():
+    """Three training steps on the GPU against the oracle's Adam recursion
+    (pinned by a hand-worked three-step example) fed the GPU's own gradients
+    of each step: every parameter after every step, which checks the moment
+    decay, the carried-over second moment and both bias corrections."""
+    from paper_1603_08161_amd import Net
+    dims = (10, 9, 8)
+    n = dims[0] * dims[1] * dims[2]
+    v0 = _params(11)
+    nt = Net(dims)
+    nt.set_params(v0)
+    bits = _input(12, dims, 1)
+    rng = np.random.default_rng(13)
+    lr = 1e-3
+    p = {"w": v0.astype(np.float64)}
+    m = {"w": np.zeros_like(p["w"])}
+    v = {"w": np.zeros_like(p["w"])}
+    for t in range(1, 4):
+        target = rng.normal(size=(1, 3, n)).astype(np.float32)
+        _, g = nt.gradients(bits, target)  # the gradient train_step computes
+        nt.train_step(bits, target, lr=lr)
+        p, m, v = onet.adam_step(p, {"w": g.astype(np.float64)}, m, v, t, lr=lr)
+        got = nt.get_params().astype(np.float64)
+        ulp = np.spacing(np.abs(p["w"]).astype(np.float32)).astype(np.float64)
+        err = np.abs(got - p["w"])
+        print(f"adam step {t}: max |dp| = {err.max():.3e}, max err/(1e-5 lr + 2 ulp) = "
+              f"{(err / (1e-5 * lr + 2 * ulp)).max():.3f}")
+        assert np.all(err <= 1e-5 * lr + 2 * ulp), t
+        # the step after t = 1 is no longer +-lr: the recursion is exercised
+        assert t == 1 or np.abs(np.abs(got - v0) - t * lr).max() > 1e-2 * lr

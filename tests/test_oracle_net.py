@@ -150,3 +150,37 @@ def test_bf16_round():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -6
     assert r[3] == -3.140625
     assert abs(r[4] - 1e-3) <= 1e-3 * 2 ** -8
+
+
+def _hand(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")) as fh:
+        return json.load(fh)[name]
+
+
+def test_adam_three_steps_match_hand_computation():
+    """Three Adam steps on one scalar with gradients 0.5, -2, 1e-3, worked out
+    by hand (tests/golden/hand_examples.json): pins the moment recursions
+    (m and v decayed and carried over) and both bias corrections, which the
+    first step from zero moments cannot distinguish."""
+    h = _hand("adam_three_steps")
+    p = {"w": np.array([h["p0"]])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    for t, g in enumerate(h["grads"], start=1):
+        p, m, v = net.adam_step(p, {"w": np.array([g])}, m, v, t, lr=h["lr"], b1=h["beta1"],
+                                b2=h["beta2"], eps=h["eps"])
+        assert abs(m["w"][0] - h["m"][t - 1]) <= 1e-15
+        assert abs(v["w"][0] - h["v"][t - 1]) <= 1e-17
+        assert abs(p["w"][0] - h["p"][t - 1]) <= 1e-14, (t, p["w"][0], h["p"][t - 1])
+
+
+def test_mse_loss_matches_hand_computation():
+    """Loss normalisation: squared error summed over components, averaged over
+    nodes (hand example in tests/golden/hand_examples.json)."""
+    h = _hand("mse_two_nodes")
+    target = np.array(h["target"])
+    loss, dout = net.mse_loss(np.zeros_like(target), target)
+    assert loss == h["loss"]
+    np.testing.assert_array_equal(dout, np.array(h["dout"]))
