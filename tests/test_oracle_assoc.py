@@ -1,0 +1,193 @@
+"""Pins of the oracle's projective association (Sec. 5.1) and of its dense
+projective ICP for the global pose (Sec. 4, Sec. 6), against what geometry
+fixes: exact plane normals from back-projected planar depth maps, closed-form
+kernel weights, the pruning boundaries, recovery of a known rigid motion of a
+box corner, the Gauss-Newton step against a least-squares solve of the
+linearised problem, and Rodrigues' formula against scipy's rotation vectors."""
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle import assoc
+from synth.scenes import (BOX_PLANES, CAM, make_box_frame, moved_planes, random_rotation,
+                          render_planes)
+
+CAMERA = assoc.Camera(**CAM)
+SMALL = assoc.Camera(width=32, height=24, fx=30.0, fy=28.0, cx=15.3, cy=11.7)
+
+
+def _ray(cam, u, v):
+    return np.array([(u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy, 1.0])
+
+
+def test_fronto_parallel_plane_closed_form():
+    """Constant depth Z0: the measured normal is exactly (0, 0, -1), a model
+    point at a pixel centre on the plane is its own target (Phi_d = 1), a
+    model normal equal to the measured one gives Phi_n = 1, and
+    Phi_v = 1 - (1 - Z0 / |p|) / eps_v."""
+    Z0 = 1.3
+    depth = np.full((SMALL.height, SMALL.width), Z0)
+    prm = assoc.AssocParams(eps_d=0.05, eps_n=0.5, eps_v=0.9)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        u = int(rng.integers(1, SMALL.width - 1))
+        v = int(rng.integers(1, SMALL.height - 1))
+        p = _ray(SMALL, u, v) * Z0
+        pa, na, w, idx = assoc.associate_one(SMALL, depth, p, [0.0, 0.0, -1.0], prm)
+        assert idx == v * SMALL.width + u
+        np.testing.assert_allclose(na, [0.0, 0.0, -1.0], atol=1e-15)
+        np.testing.assert_allclose(pa, p, rtol=0, atol=1e-15)
+        phi_v = 1.0 - (1.0 - Z0 / np.linalg.norm(p)) / prm.eps_v
+        assert w == pytest.approx(((2.0 + phi_v) / 3.0) ** 2, rel=1e-14)
+
+
+def test_tilted_planes_give_exact_normals():
+    """Back-projected pixels of a planar depth map lie on the plane, so the
+    cross product of their differences is the plane normal (facing the
+    camera) at every interior pixel."""
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        m = rng.normal(size=3)
+        m[2] = -abs(m[2]) - 1.0
+        m /= np.linalg.norm(m)
+        depth = render_planes(CAM, [(m, -1.0)], dtype=np.float64)
+        for _ in range(30):
+            u = int(rng.integers(1, CAMERA.width - 1))
+            v = int(rng.integers(1, CAMERA.height - 1))
+            n = assoc.measured_normal(CAMERA, depth, u, v)
+            assert n is not None
+            np.testing.assert_allclose(n, m, atol=1e-9)
+
+
+def test_pruning_boundaries_and_invalid_pixels():
+    Z0 = 2.0
+    depth = np.full((SMALL.height, SMALL.width), Z0)
+    depth[5, 7] = 0.0
+    prm = assoc.AssocParams(eps_d=0.25, eps_n=0.5, eps_v=1.0)
+    u, v = 12, 9
+    base = _ray(SMALL, u, v) * Z0
+    n = np.array([0.0, 0.0, -1.0])
+    # moved along z by exactly eps_d: Phi_d = 0 is kept (pruning is Phi < 0)
+    p = base + np.array([0.0, 0.0, 0.25])
+    # same pixel? scale along the ray keeps the pixel; moving along z changes
+    # the projection, so move along the ray instead to hit the same pixel
+    p = base * (1.0 + 0.25 / Z0)
+    d = np.linalg.norm(p - base)
+    prm_edge = assoc.AssocParams(eps_d=d, eps_n=0.5, eps_v=1.0)
+    _, _, w_edge, idx = assoc.associate_one(SMALL, depth, p, n, prm_edge)
+    assert idx == v * SMALL.width + u and w_edge > 0.0
+    prm_in = assoc.AssocParams(eps_d=d * (1 - 1e-12), eps_n=0.5, eps_v=1.0)
+    assert assoc.associate_one(SMALL, depth, p, n, prm_in)[2] == 0.0
+    # normal deviation: a model normal tilted by 60 degrees has 1 - cos = 0.5
+    tilt = np.array([np.sin(np.pi / 3), 0.0, -np.cos(np.pi / 3)])
+    assert assoc.associate_one(SMALL, depth, base, tilt, prm)[2] > 0.0
+    prm_n = assoc.AssocParams(eps_d=0.25, eps_n=0.49, eps_v=1.0)
+    assert assoc.associate_one(SMALL, depth, base, tilt, prm_n)[2] == 0.0
+    # no measurement at the pixel, or at a neighbour of it (no normal)
+    p_hole = _ray(SMALL, 7, 5) * Z0
+    assert assoc.associate_one(SMALL, depth, p_hole, n, prm)[2] == 0.0
+    p_nb = _ray(SMALL, 8, 5) * Z0
+    assert assoc.associate_one(SMALL, depth, p_nb, n, prm)[2] == 0.0
+    # border pixel (no full neighbourhood), outside the image, behind the camera
+    assert assoc.associate_one(SMALL, depth, _ray(SMALL, 0, 5) * Z0, n, prm)[2] == 0.0
+    out = assoc.associate_one(SMALL, depth, _ray(SMALL, 40, 5) * Z0, n, prm)
+    assert out[2] == 0.0 and out[3] == -1
+    assert assoc.associate_one(SMALL, depth, -base, n, prm)[3] == -1
+
+
+def test_vectorised_equals_per_sample_loop():
+    """The vectorised association computes each sample exactly as the
+    per-sample definition does (bit for bit)."""
+    rng = np.random.default_rng(2)
+    vv, uu = np.mgrid[0:SMALL.height, 0:SMALL.width]
+    depth = 1.2 + 0.05 * np.sin(0.3 * uu + 0.2 * vv) + 0.002 * rng.normal(size=uu.shape)
+    depth[rng.uniform(size=depth.shape) < 0.03] = 0.0
+    u = rng.uniform(-2, SMALL.width + 2, 400)
+    v = rng.uniform(-2, SMALL.height + 2, 400)
+    z = rng.uniform(1.0, 1.4, 400)
+    pts = np.stack([(u - SMALL.cx) / SMALL.fx * z, (v - SMALL.cy) / SMALL.fy * z, z], axis=1)
+    pts[::37, 2] *= -1
+    nrm = rng.normal(scale=0.3, size=(400, 3))
+    nrm[:, 2] = -1.0
+    nrm[::41] = 0.0
+    prm = assoc.AssocParams(eps_d=0.2, eps_n=0.6, eps_v=0.8)
+    a = assoc.associate(SMALL, depth, pts, nrm, prm)
+    b = assoc.associate_loop(SMALL, depth, pts, nrm, prm)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    assert (a[2] > 0).sum() > 50 and (a[2] == 0).sum() > 50
+
+
+def test_rodrigues_matches_rotation_vectors():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        w = rng.normal(size=3) * rng.uniform(0, 3)
+        np.testing.assert_allclose(assoc.rodrigues(w), Rotation.from_rotvec(w).as_matrix(),
+                                   atol=1e-14)
+    np.testing.assert_array_equal(assoc.rodrigues(np.zeros(3)), np.eye(3))
+
+
+def test_gauss_newton_step_solves_the_linearised_problem():
+    """With the association of the first iteration fixed, the step xi
+    minimises sum w (r + J xi)^2: compare with a least-squares solve (QR) of
+    the stacked weighted rows, which does not use the normal equations."""
+    rng = np.random.default_rng(4)
+    Q = Rotation.from_rotvec(np.deg2rad(0.8) * np.array([0.3, -0.5, 0.8])).as_matrix()
+    c = np.array([0.004, -0.006, 0.005])
+    f = make_box_frame(Q, c, step=9)
+    cam = assoc.Camera(**f.camera)
+    prm = assoc.AssocParams(eps_d=0.05, eps_n=0.3, eps_v=0.95)
+    pts = f.model_canon.astype(np.float64)
+    nrm = f.model_normal.astype(np.float64)
+    pa, na, w, _ = assoc.associate(cam, f.depth, pts, nrm, prm)
+    keep = w > 0
+    r = np.einsum("ca,ca->c", na, pts - pa)[keep]
+    J = np.concatenate([np.cross(pts, na), na], axis=1)[keep]
+    sw = np.sqrt(w[keep])
+    xi_ls = np.linalg.lstsq(J * sw[:, None], -r * sw, rcond=None)[0]
+    R1, t1, E0, cnt = assoc.icp_step(cam, f.depth, pts, nrm, prm, np.eye(3), np.zeros(3))
+    assert cnt == keep.sum() > 1000
+    np.testing.assert_allclose(R1, assoc.rodrigues(xi_ls[:3]), atol=1e-12)
+    np.testing.assert_allclose(t1, xi_ls[3:], atol=1e-12)
+    assert E0 == pytest.approx(float(np.sum(w[keep] * r * r)), rel=1e-12)
+    del rng
+
+
+def test_icp_recovers_a_known_rigid_motion():
+    """Depth of the box corner after (Q, c); model samples from the unmoved
+    corner: the ICP pose converges to (Q, c), and the energy falls to ~0."""
+    rng = np.random.default_rng(5)
+    axis = rng.normal(size=3)
+    Q = Rotation.from_rotvec(np.deg2rad(1.5) * axis / np.linalg.norm(axis)).as_matrix()
+    c = np.array([0.008, -0.005, 0.012])
+    f = make_box_frame(Q, c)
+    cam = assoc.Camera(**f.camera)
+    prm = assoc.AssocParams(eps_d=0.05, eps_n=0.3, eps_v=0.95)
+    R, t, hist = assoc.rigid_pose(cam, f.depth, f.model_canon, f.model_normal, prm, 10)
+    ang = np.linalg.norm(Rotation.from_matrix(R @ Q.T).as_rotvec())
+    print("ICP history (E, count):", hist)
+    assert ang < 1e-5 and np.abs(t - c).max() < 1e-5
+    assert hist[-1][0] < 1e-9 * hist[0][0]
+    es = [e for e, _ in hist]
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(es, es[1:]))
+
+
+def test_icp_stays_at_the_true_pose():
+    f = make_box_frame()
+    cam = assoc.Camera(**f.camera)
+    prm = assoc.AssocParams(eps_d=0.05, eps_n=0.3, eps_v=0.95)
+    R, t, hist = assoc.rigid_pose(cam, f.depth, f.model_canon, f.model_normal, prm, 3)
+    assert np.abs(R - np.eye(3)).max() < 1e-6 and np.abs(t).max() < 1e-6
+
+
+def test_moved_planes_render_the_moved_region():
+    """Generator check: a point on an unmoved face, moved by (Q, c), lies on
+    the moved face's plane."""
+    rng = np.random.default_rng(6)
+    Q = random_rotation(rng)
+    c = rng.normal(size=3) * 0.01
+    for (m, b), (mq, bq) in zip(BOX_PLANES, moved_planes(BOX_PLANES, Q, c)):
+        x = rng.normal(size=3)
+        x -= (m @ x - b) * m
+        assert abs(mq @ (Q @ x + c) - bq) < 1e-12
