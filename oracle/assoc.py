@@ -244,12 +244,24 @@ def rodrigues(w: np.ndarray) -> np.ndarray:
     return np.eye(3) + np.sin(th) * K + (1.0 - np.cos(th)) * (K @ K)
 
 
+def transform(points: np.ndarray, normals: np.ndarray, R: np.ndarray, t: np.ndarray):
+    """q = R p + t and R n, each component summed left to right as written
+    (reading A5: the association decisions that follow depend on the bits)."""
+    p = np.asarray(points, np.float64).reshape(-1, 3)
+    n = np.asarray(normals, np.float64).reshape(-1, 3)
+    q = np.empty_like(p)
+    nq = np.empty_like(n)
+    for r in range(3):
+        q[:, r] = R[r, 0] * p[:, 0] + R[r, 1] * p[:, 1] + R[r, 2] * p[:, 2] + t[r]
+        nq[:, r] = R[r, 0] * n[:, 0] + R[r, 1] * n[:, 1] + R[r, 2] * n[:, 2]
+    return q, nq
+
+
 def icp_step(cam: Camera, depth: np.ndarray, points: np.ndarray, normals: np.ndarray,
              prm: AssocParams, R: np.ndarray, t: np.ndarray):
     """One Gauss-Newton iteration of the projective point-to-plane ICP.
     Returns (R', t', E at (R, t), number of associated samples)."""
-    q = np.asarray(points, np.float64) @ R.T + t
-    nq = np.asarray(normals, np.float64) @ R.T
+    q, nq = transform(np.asarray(points, np.float64), np.asarray(normals, np.float64), R, t)
     pa, na, w, _ = associate(cam, depth, q, nq, prm)
     keep = w > 0.0
     r = _dot(na, q - pa)

@@ -138,3 +138,29 @@ def solve_frame_icp(spec, frame: Dict, prm: assoc.AssocParams, icp_iters: int,
         if history is not None:
             history.append((np.array(out["energy"], np.float64), int(np.count_nonzero(w))))
     return out
+
+
+def track_frame(spec, frame: Dict, prm: assoc.AssocParams, rigid_iters: int, icp_iters: int,
+                state=None, pose=None, history: Optional[List] = None):
+    """One tracked frame with the global pose found first (Sec. 6): the
+    model samples deformed by the lattice state (in the lattice frame) run
+    `rigid_iters` projective ICP iterations from `pose` (12 floats, R
+    row-major then t; None: identity), then ``solve_frame_icp`` runs with
+    that pose.  Returns (solve result, pose, rigid-ICP history)."""
+    grids = level_grids(spec.dims, spec.spacing, spec.origin, spec.num_levels)
+    finest = grids[-1]
+    if state is None:
+        t, R = rest_state(finest)
+    else:
+        t = np.asarray(state[0], np.float64).reshape(-1, 3)
+        R = np.asarray(state[1], np.float64).reshape(-1, 3, 3)
+    P = _identity_pose() if pose is None else np.asarray(pose, np.float64).reshape(12)
+    cam = assoc.Camera(**frame["camera"])
+    q, nq = deform_samples(finest, t - finest.rest_positions(), R, frame["model_canon"],
+                           frame["model_normal"], _identity_pose())
+    Rg, tg, hist = assoc.rigid_pose(cam, frame["depth"], q, nq, prm, rigid_iters,
+                                    P[:9].reshape(3, 3), P[9:])
+    P = np.concatenate([Rg.ravel(), tg])
+    out = solve_frame_icp(spec, dict(frame, pose=P), prm, icp_iters, state=(t, R),
+                          history=history)
+    return out, P, hist

@@ -123,3 +123,21 @@ def test_tracked_frame_recovers_a_rigid_motion():
     print("dense energy at rest", e0, "per round:", e, "associated:", [h[1] for h in hist])
     assert e[-1] < 0.05 * e0
     assert np.isfinite(out["t"]).all()
+
+
+def test_tracked_frame_with_pose_explains_a_rigid_motion_by_the_pose():
+    """The box corner moved rigidly by (Q, c): the pose found first (Sec. 6)
+    recovers (Q, c), so the non-rigid rounds that follow leave the lattice at
+    rest (a rigid motion costs the lattice nothing once the pose holds it)."""
+    spec = _box_lattice(n=8, gn=2, pcg=10)
+    rng = np.random.default_rng(4)
+    Q = Rotation.from_rotvec(np.deg2rad(1.0) * rng.normal(size=3) / 1.7).as_matrix()
+    c = np.array([0.006, 0.004, -0.005])
+    f = make_box_frame(Q, c, step=9)
+    out, P, hist = track.track_frame(spec, _frame_dict(f), PRM, rigid_iters=8, icp_iters=1)
+    np.testing.assert_allclose(P[:9].reshape(3, 3), Q, atol=1e-5)
+    np.testing.assert_allclose(P[9:], c, atol=1e-5)
+    assert hist[-1][0] < 1e-6 * hist[0][0]
+    g = _grid(spec)
+    disp = out["t"] - g.rest_positions()
+    assert np.abs(disp).max() < 1e-4 * spec.spacing * 100
