@@ -45,8 +45,13 @@ with weights and targets held fixed, linearised in a small rotation w and
 translation tau applied after the current pose, q -> q + w x q + tau:
   r_c = n^a . (q_c - p^a),   J_c = [q_c x n^a, n^a],   (sum w J J^T) xi = -sum w J r.
 The update is R <- Rot(w) R, t <- Rot(w) t + tau with Rot(w) the rotation by
-|w| about w / |w| (Rodrigues).  Reading A6: when the 6x6 system is singular
-(fewer than six independent constraints) the pose is left unchanged.
+|w| about w / |w| (Rodrigues).  Reading A6: when fewer than six pairs survive
+or the 6x6 system is numerically singular -- rank below 6 at the tolerance
+1e-8 times its largest diagonal entry -- the pose is left unchanged.  (A
+single plane constrains 3 of the 6 unknowns; float32 depth quantisation tilts
+its measured normals by about 1e-5, which leaves eigenvalues near 1e-11 of
+the largest instead of 0, and a step along them would be driven by that
+noise; three planes at large angles give about 1e-2.)
 """
 
 from __future__ import annotations
@@ -269,7 +274,7 @@ def icp_step(cam: Camera, depth: np.ndarray, points: np.ndarray, normals: np.nda
     J = np.concatenate([_cross(q, na), na], axis=1)[keep]
     H = (J * w[keep, None]).T @ J
     g = (J * w[keep, None]).T @ r[keep]
-    if int(keep.sum()) < 6 or np.linalg.matrix_rank(H) < 6:
+    if int(keep.sum()) < 6 or np.linalg.matrix_rank(H, tol=1e-8 * np.max(np.diag(H))) < 6:
         return R.copy(), t.copy(), E, int(keep.sum())
     xi = -np.linalg.solve(H, g)
     Q = rodrigues(xi[:3])

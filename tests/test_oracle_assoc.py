@@ -191,3 +191,28 @@ def test_moved_planes_render_the_moved_region():
         x = rng.normal(size=3)
         x -= (m @ x - b) * m
         assert abs(mq @ (Q @ x + c) - bq) < 1e-12
+
+
+def test_single_plane_system_is_singular_and_keeps_the_pose():
+    """Reading A6: a single plane constrains 3 of the 6 pose unknowns; the
+    6x6 system's smallest eigenvalues sit near float32 depth noise (far below
+    1e-8 of the largest diagonal entry), so the pose is left unchanged."""
+    m = np.array([0.2, -0.1, -1.0])
+    m /= np.linalg.norm(m)
+    depth = render_planes(CAM, [(m, -0.9)])
+    vv, uu = np.mgrid[8:CAMERA.height - 8:9, 8:CAMERA.width - 8:9]
+    z = depth[vv, uu].astype(np.float64)
+    pts = np.stack([(uu + 0.5 - CAMERA.cx) * z / CAMERA.fx,
+                    (vv + 0.5 - CAMERA.cy) * z / CAMERA.fy, z], -1).reshape(-1, 3) + 0.002 * m
+    nrm = np.broadcast_to(m, pts.shape)
+    prm = assoc.AssocParams(eps_d=0.05, eps_n=0.3, eps_v=0.95)
+    pa, na, w, _ = assoc.associate(CAMERA, depth, pts, nrm, prm)
+    keep = w > 0
+    J = np.concatenate([assoc._cross(pts, na), na], axis=1)[keep]
+    H = (J * w[keep, None]).T @ J
+    ev = np.linalg.eigvalsh(H)
+    assert ev[2] < 1e-9 * np.max(np.diag(H)) and ev[3] > 1e-4 * np.max(np.diag(H))
+    R, t, hist = assoc.rigid_pose(CAMERA, depth, pts, nrm, prm, 2)
+    np.testing.assert_array_equal(R, np.eye(3))
+    np.testing.assert_array_equal(t, np.zeros(3))
+    assert hist[0][1] == int(keep.sum()) > 6
