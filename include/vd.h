@@ -30,9 +30,10 @@
  *   - Work is issued on the stream given at creation (a hipStream_t passed as
  *     void*; NULL = the null stream).  One handle must not be used by two host
  *     threads at once.
- *   - The global rigid pose (R, t of Sec. 4) is not part of this path: the
- *     caller expresses targets and normals in the frame where it is the
- *     identity.
+ *   - vd_set_constraints takes targets and normals in the lattice frame,
+ *     where the global rigid pose (R, t of Sec. 4) is the identity; the pose
+ *     and the projective association that produce such constraints from a
+ *     depth map are in vd_track.h.
  */
 #ifndef VD_H
 #define VD_H
@@ -53,8 +54,10 @@ extern "C" {
 
 /* ---- precision modes (arithmetic type of the node vectors) -------------- */
 #define VD_FP32_FP64RED 0 /* float32 vectors, stencil and rotations; float64
-                             CG scalars and energy sums; float64 rotation
-                             refit when the float32 fit is ill-conditioned */
+                             CG reductions and step sizes (applied to the
+                             float32 vectors as two float32 parts) and
+                             energy sums; float64 rotation refit when the
+                             float32 fit is ill-conditioned */
 #define VD_FP64 1         /* float64 everywhere */
 
 /* ---- pointer location --------------------------------------------------- */
@@ -222,12 +225,16 @@ int vd_set_constraints(vd_lattice* l, const vd_constraints* c);
  * VD_ESTATE if no constraints were set. */
 int vd_solve_frame(vd_lattice* l, const vd_solve_opts* opts, vd_solve_report* report);
 
-/* Batched solve of several independent lattices (same precision, number of
- * levels, schedule and stream; any sizes).  Every step of the frame schedule
- * is one launch covering the workgroups of all lattices, with per-lattice
- * reductions.  The batch does not own the handles: they must outlive it.
- * Creating it sets every handle's stencil tile, per level, to the tile of
- * the largest lattice at that level.  VD_EINVAL on mismatched handles. */
+/* Batched solve of several independent lattices (same number of levels,
+ * schedule, stream and VD_FLAG_GRAPH setting; any sizes and either
+ * precision).  Every step of the frame schedule is one launch covering the
+ * workgroups of all lattices of one precision, with per-lattice reductions;
+ * the float64 lattices, if any, form a second part that runs on a
+ * library-owned stream forked from the lattices' stream and joined back into
+ * it, so both parts overlap on the GPU.  The batch does not own the handles:
+ * they must outlive it.  Creating it sets every handle's stencil tile, per
+ * level, to the tile of the largest lattice of its part at that level.
+ * VD_EINVAL on mismatched handles. */
 int vd_batch_create(vd_lattice* const* lattices, int32_t n, vd_batch** out);
 
 /* Solve one frame of every lattice of the batch (Sec. 7, as vd_solve_frame);

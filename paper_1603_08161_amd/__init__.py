@@ -1,7 +1,7 @@
 """MI355X (gfx950) implementation of the VolumeDeform lattice solve.
 
 The solver and the warm-start network live in the HIP library ``libvd.so``
-(C-ABI: ``include/vd.h``, ``include/vd_net.h``);
+(C-ABI: ``include/vd.h``, ``include/vd_net.h``, ``include/vd_track.h``);
 this package is its Python binding.  Importing it loads the library and fails
 loudly if it has not been built.
 """
@@ -12,6 +12,9 @@ from ._lib import (  # noqa: F401
     Batch,
     Lattice,
     Net,
+    associate,
+    batch_precision,
+    rigid_pose,
     VDError,
     fit_rotations,
     lib,

@@ -1,4 +1,5 @@
-"""ctypes binding of libvd.so (the C-ABI in include/vd.h and include/vd_net.h).
+"""ctypes binding of libvd.so (the C-ABI in include/vd.h, include/vd_net.h and
+include/vd_track.h).
 
 Argument marshalling only: every step of the solve runs in the library's HIP
 kernels.  Arrays may be numpy (host memory) or torch CUDA tensors (device
@@ -46,8 +47,10 @@ EXPORTED = (
     "vd_batch_create", "vd_batch_solve", "vd_batch_destroy", "vd_batch_profile",
     "vd_get_profile", "vd_warm_features", "vd_net_param_count", "vd_net_create", "vd_net_destroy",
     "vd_net_set_params", "vd_net_get_params", "vd_net_forward", "vd_net_gradients",
-    "vd_net_train_step",
+    "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
+    "vd_set_pose", "vd_track_frame", "vd_debug_associate",
 )
+VD_TRACK_MAX_ITERS = 64
 
 
 class LatticeDesc(C.Structure):
@@ -110,6 +113,70 @@ class SolveReport(C.Structure):
     ]
 
 
+class Camera(C.Structure):
+    _fields_ = [
+        ("width", C.c_int32),
+        ("height", C.c_int32),
+        ("fx", C.c_double),
+        ("fy", C.c_double),
+        ("cx", C.c_double),
+        ("cy", C.c_double),
+    ]
+
+
+class AssocParams(C.Structure):
+    _fields_ = [("eps_d", C.c_double), ("eps_n", C.c_double), ("eps_v", C.c_double)]
+
+
+class DepthFrameC(C.Structure):
+    _fields_ = [
+        ("camera", Camera),
+        ("depth", C.c_void_p),
+        ("n_model", C.c_int64),
+        ("model_canon", C.c_void_p),
+        ("model_normal", C.c_void_p),
+        ("n_sparse", C.c_int64),
+        ("sparse_canon", C.c_void_p),
+        ("sparse_target", C.c_void_p),
+        ("assoc", AssocParams),
+        ("mem", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class TrackOpts(C.Structure):
+    _fields_ = [
+        ("rigid_iters", C.c_int32),
+        ("icp_iters", C.c_int32),
+        ("reset_to_rest", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class TrackReport(C.Structure):
+    _fields_ = [
+        ("energy", C.c_double * 4),
+        ("pose", C.c_double * 12),
+        ("rigid_hist", C.c_double * (2 * VD_TRACK_MAX_ITERS)),
+        ("assoc_kept", C.c_int32 * VD_TRACK_MAX_ITERS),
+        ("bits", C.c_uint32),
+        ("reserved", C.c_int32),
+    ]
+
+
+def _camera(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    return c
+
+
+def _assoc(eps) -> AssocParams:
+    a = AssocParams()
+    a.eps_d, a.eps_n, a.eps_v = (float(e) for e in eps)
+    return a
+
+
 class VDError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
@@ -155,6 +222,15 @@ def _load() -> C.CDLL:
         "vd_net_forward": ([vp, vp, i32, vp, i32], C.c_int),
         "vd_net_gradients": ([vp, vp, vp, i32, vp, dp, i32], C.c_int),
         "vd_net_train_step": ([vp, vp, vp, i32, C.c_float, i32, dp], C.c_int),
+        "vd_associate": ([C.POINTER(Camera), vp, vp, vp, i64, C.POINTER(AssocParams), vp, vp, vp,
+                          vp, i32, vp], C.c_int),
+        "vd_rigid_pose": ([C.POINTER(Camera), vp, vp, vp, i64, C.POINTER(AssocParams), i32, vp, vp,
+                           i32, vp], C.c_int),
+        "vd_set_depth_frame": ([vp, C.POINTER(DepthFrameC)], C.c_int),
+        "vd_get_pose": ([vp, dp], C.c_int),
+        "vd_set_pose": ([vp, dp], C.c_int),
+        "vd_track_frame": ([vp, C.POINTER(TrackOpts), C.POINTER(TrackReport)], C.c_int),
+        "vd_debug_associate": ([vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -397,6 +473,64 @@ class Lattice:
         del keep
 
     # ---- test entry points ------------------------------------------
+    # ---- tracking (vd_track.h) --------------------------------------------
+    def set_depth_frame(self, frame, sparse_canon=None, sparse_target=None,
+                        eps=(0.05, 0.3, 0.95)) -> None:
+        """Upload one sensor frame (depth map, camera, canonical model samples
+        and normals; optional sparse pairs with camera-frame targets)."""
+        ptrs, mem, keep = _prep([frame.depth, frame.model_canon, frame.model_normal,
+                                 sparse_canon, sparse_target])
+        f = DepthFrameC()
+        f.camera = _camera(frame.camera)
+        f.depth = ptrs[0]
+        f.n_model = int(frame.model_canon.shape[0])
+        f.model_canon, f.model_normal = ptrs[1], ptrs[2]
+        f.n_sparse = 0 if sparse_canon is None else int(sparse_canon.shape[0])
+        f.sparse_canon, f.sparse_target = ptrs[3], ptrs[4]
+        f.assoc = _assoc(eps)
+        f.mem = mem
+        _check(_lib.vd_set_depth_frame(self._h, C.byref(f)), "vd_set_depth_frame")
+        self.n_model = int(f.n_model)
+        del keep
+
+    def get_pose(self) -> np.ndarray:
+        out = (C.c_double * 12)()
+        _check(_lib.vd_get_pose(self._h, out), "vd_get_pose")
+        return np.array(out[:])
+
+    def set_pose(self, pose) -> None:
+        arr = (C.c_double * 12)(*[float(x) for x in np.asarray(pose, np.float64).ravel()])
+        _check(_lib.vd_set_pose(self._h, arr), "vd_set_pose")
+
+    def track_frame(self, rigid_iters: int = 0, icp_iters: int = 1, reset: bool = False,
+                    report: bool = True):
+        o = TrackOpts()
+        o.rigid_iters, o.icp_iters, o.reset_to_rest = int(rigid_iters), int(icp_iters), int(reset)
+        if not report:
+            _check(_lib.vd_track_frame(self._h, C.byref(o), None), "vd_track_frame")
+            return None
+        r = TrackReport()
+        _check(_lib.vd_track_frame(self._h, C.byref(o), C.byref(r)), "vd_track_frame")
+        return {"energy": np.array(r.energy[:]), "pose": np.array(r.pose[:]),
+                "rigid_hist": np.array(r.rigid_hist[:2 * o.rigid_iters]).reshape(-1, 2),
+                "assoc_kept": np.array(r.assoc_kept[:o.icp_iters]), "bits": int(r.bits)}
+
+    def debug_associate(self, disp, rot):
+        """Association of the frame's model samples at a finest state
+        (displacements (N,3), rotations (N,3,3)) and the handle's pose."""
+        n = self.n_model
+        d = np.ascontiguousarray(disp, np.float32).reshape(-1)
+        R = np.ascontiguousarray(rot, np.float32).reshape(-1)
+        t = np.empty((n, 3), np.float32)
+        nn = np.empty((n, 3), np.float32)
+        w = np.empty(n, np.float32)
+        px = np.empty(n, np.int32)
+        _check(_lib.vd_debug_associate(self._h, d.ctypes.data, R.ctypes.data, t.ctypes.data,
+                                       nn.ctypes.data, w.ctypes.data, px.ctypes.data,
+                                       VD_MEM_HOST), "vd_debug_associate")
+        return t, nn, w, px
+
+    # ------------------------------------------------------------------
     def debug_apply(self, level: int, p) -> np.ndarray:
         n = self.n_nodes(level)
         p = _host(p)
@@ -481,6 +615,54 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def associate(cam, depth, points, normals, eps, stream: Optional[int] = None):
+    """Projective association of camera-frame samples (host arrays):
+    returns (target (n,3), normal (n,3), weight (n,), pixel (n,))."""
+    d = np.ascontiguousarray(depth, np.float32)
+    p = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+    q = np.ascontiguousarray(normals, np.float32).reshape(-1, 3)
+    n = p.shape[0]
+    t = np.empty((n, 3), np.float32)
+    nn = np.empty((n, 3), np.float32)
+    w = np.empty(n, np.float32)
+    px = np.empty(n, np.int32)
+    c, a = _camera(cam), _assoc(eps)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_associate(C.byref(c), d.ctypes.data, p.ctypes.data, q.ctypes.data, n,
+                             C.byref(a), t.ctypes.data, nn.ctypes.data, w.ctypes.data,
+                             px.ctypes.data, VD_MEM_HOST, C.c_void_p(s)), "vd_associate")
+    return t, nn, w, px
+
+
+def rigid_pose(cam, depth, points, normals, eps, iters: int, pose=None,
+               stream: Optional[int] = None):
+    """Rigid pose by projective ICP (host arrays): returns (pose (12,),
+    history (iters, 2) of E and kept pairs)."""
+    d = np.ascontiguousarray(depth, np.float32)
+    p = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+    q = np.ascontiguousarray(normals, np.float32).reshape(-1, 3)
+    P = np.ascontiguousarray(
+        np.concatenate([np.eye(3).ravel(), np.zeros(3)]) if pose is None else pose, np.float64)
+    hist = np.zeros((max(iters, 1), 2), np.float64)
+    c, a = _camera(cam), _assoc(eps)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_rigid_pose(C.byref(c), d.ctypes.data, p.ctypes.data, q.ctypes.data,
+                              p.shape[0], C.byref(a), int(iters), P.ctypes.data,
+                              hist.ctypes.data, VD_MEM_HOST, C.c_void_p(s)), "vd_rigid_pose")
+    return P, hist[:iters]
+
+
+def batch_precision(n: int) -> str:
+    """Precision a batched lattice with n nodes per axis is given by the
+    benchmark and the tests: float32 truncated CG (20 iterations) amplifies
+    its rounding by about an order of magnitude per iteration once its Ritz
+    values settle, and on lattices below 33 nodes per axis that leaves the
+    final energy and positions outside 1e-4 / 1e-3 of the spacing of the
+    float64 replica; those lattices are latency-bound, so float64 costs them
+    no time."""
+    return "fp64" if int(n) < 33 else "fp32"
 
 
 def fit_rotations(M, R_prev=None, precision: str = "fp32", stream: Optional[int] = None):

@@ -17,7 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvd.so")
-SOURCES = ["kernels.hip", "solve.hip", "sort.hip", "net.hip", "api.hip"]
+SOURCES = ["kernels.hip", "solve.hip", "sort.hip", "net.hip", "track.hip", "api.hip"]
+# track.hip takes its association decisions in float64 in the written operation
+# order, so no product may be fused into a following sum there.
+EXTRA_FLAGS = {"track.hip": ["-ffp-contract=off"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -43,7 +46,8 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+               "-o", obj]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr}")

@@ -11,7 +11,9 @@
 
 #include "../../include/vd.h"
 #include "../../include/vd_net.h"
+#include "../../include/vd_track.h"
 #include "net_kernels.h"
+#include "track_kernels.h"
 #include "vd_device.h"
 #include "vd_kernels.h"
 
@@ -180,6 +182,23 @@ int bits_for(int n) {
   return b;
 }
 
+// Camera and association thresholds of the C-ABI, checked.
+int camera_of(const vd_camera* c, const vd_assoc_params* a, CamAssoc* out) {
+  if (!c || !a) return VD_EINVAL;
+  if (c->width < 3 || c->height < 3 || (int64_t)c->width * c->height > (1ll << 30))
+    return VD_EINVAL;
+  const double v[7] = {c->fx, c->fy, c->cx, c->cy, a->eps_d, a->eps_n, a->eps_v};
+  for (double x : v)
+    if (!std::isfinite(x)) return VD_EINVAL;
+  if (!(c->fx > 0.0) || !(c->fy > 0.0) || !(a->eps_d > 0.0) || !(a->eps_n > 0.0) ||
+      !(a->eps_v > 0.0))
+    return VD_EINVAL;
+  out->W = c->width; out->H = c->height;
+  out->fx = c->fx; out->fy = c->fy; out->cx = c->cx; out->cy = c->cy;
+  out->eps_d = a->eps_d; out->eps_n = a->eps_n; out->eps_v = a->eps_v;
+  return VD_OK;
+}
+
 }  // namespace
 
 class ISolver {
@@ -202,6 +221,12 @@ class ISolver {
   virtual int tune(int iters, int* tile_out, double* us_out) = 0;
   virtual int warm_features(const float* prev2, uint16_t* x, int mem) = 0;
   virtual int profile(double* us, int* n) = 0;
+  virtual int set_depth_frame(const vd_depth_frame* f) = 0;
+  virtual int get_pose(double* pose) = 0;
+  virtual int set_pose(const double* pose) = 0;
+  virtual int track_frame(const vd_track_opts* o, vd_track_report* r) = 0;
+  virtual int debug_associate(const float* disp, const float* rot, float* target, float* normal,
+                              float* weight, int* pixel, int mem) = 0;
 };
 
 template <typename T>
@@ -215,6 +240,7 @@ class Solver final : public ISolver {
     if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
     if (h_flags_) (void)hipHostFree(h_flags_);
     if (h_sc_) (void)hipHostFree(h_sc_);
+    if (h_pose_) (void)hipHostFree(h_pose_);
     pool_.release_all();
   }
 
@@ -271,6 +297,10 @@ class Solver final : public ISolver {
     VD_CHECK(pool_.alloc(&d_flags_, 4));
     VD_TRY(hipHostMalloc((void**)&h_flags_, 4 * sizeof(int), hipHostMallocDefault));
     VD_TRY(hipHostMalloc((void**)&h_sc_, sizeof(Scalars), hipHostMallocDefault));
+    VD_TRY(hipHostMalloc((void**)&h_pose_, 12 * sizeof(double), hipHostMallocDefault));
+    VD_CHECK(ensure_track(0, 0, 0));
+    for (int k = 0; k < 12; ++k) h_pose_[k] = (k == 0 || k == 4 || k == 8) ? 1.0 : 0.0;
+    VD_TRY(hipMemcpyAsync(pose_d_, h_pose_, 12 * sizeof(double), hipMemcpyHostToDevice, stream_));
     VD_TRY(launch_set_rest<T>(nodes_of(finest().view(desc_.w_arap)), stream_));
     VD_TRY(hipStreamSynchronize(stream_));
     return VD_OK;
@@ -312,20 +342,30 @@ class Solver final : public ISolver {
     VD_TRY(hipStreamSynchronize(stream_));
     if (h_flags_[0] & 1) return VD_EINVAL;
     if (h_flags_[0] & 2) return VD_ERANGE;
-    // per-level rows, binning and cell cache
+    have_frame_ = false;
+    return build_levels(raw, C, S, true);
+  }
+
+  // Per-level rows, binning and cell cache of the staged constraints.  With
+  // `structure` false only the row values are recomputed: the canonical
+  // positions (hence every row's cell, the sort by cell and the cell
+  // segments) are those of the previous build.
+  int build_levels(const RawConstraints& raw, int C, int S, bool structure) {
     const int rows = C + 3 * S;
-    VD_CHECK(ensure_rows(rows));
+    if (structure) VD_CHECK(ensure_rows(rows));
     for (int l = 0; l < L_; ++l) {
       LevelData<T>& v = lv_[l];
       const LevelView<T> V = v.view(desc_.w_arap);
       const RowView<T> R = v.rows_view(rows, C);
       VD_TRY(launch_rows<T>(raw, V, R, desc_.origin, desc_.w_dense, desc_.w_sparse, keys_in_,
                             vals_in_, stream_));
-      VD_TRY(sort_pairs(sort_temp_, sort_temp_bytes_, keys_in_, keys_out_, vals_in_, v.sorted,
-                        rows, bits_for(v.ncell), stream_));
-      VD_TRY(launch_heads(keys_out_, rows, heads_, stream_));
-      VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, heads_, scan_, rows, stream_));
-      VD_TRY(launch_segments<T>(V, R, keys_out_, scan_, v.cell_map, v.ncell, stream_));
+      if (structure) {
+        VD_TRY(sort_pairs(sort_temp_, sort_temp_bytes_, keys_in_, keys_out_, vals_in_, v.sorted,
+                          rows, bits_for(v.ncell), stream_));
+        VD_TRY(launch_heads(keys_out_, rows, heads_, stream_));
+        VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, heads_, scan_, rows, stream_));
+        VD_TRY(launch_segments<T>(V, R, keys_out_, scan_, v.cell_map, v.ncell, stream_));
+      }
       VD_TRY(launch_build_cells<T>(V, R, v.K, std::min(v.cap_cells, 8192), stream_));
       VD_TRY(launch_node_flags<T>(V, node_flags_, stream_));
       VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, node_flags_, node_scan_, v.N, stream_));
@@ -511,6 +551,172 @@ class Solver final : public ISolver {
                               d_flags_, stream_));
     VD_TRY(hipStreamSynchronize(stream_));
     energy_fresh_ = false;
+    return VD_OK;
+  }
+
+  // ---- tracking (vd_track.h) ---------------------------------------------
+  int set_depth_frame(const vd_depth_frame* f) override {
+    if (!f) return VD_EINVAL;
+    CamAssoc cam;
+    VD_CHECK(camera_of(&f->camera, &f->assoc, &cam));
+    if (f->n_model < 0 || f->n_sparse < 0) return VD_EINVAL;
+    if (f->n_model + 3 * f->n_sparse > (1ll << 30)) return VD_EINVAL;
+    if (!f->depth || (f->n_model > 0 && (!f->model_canon || !f->model_normal)) ||
+        (f->n_sparse > 0 && (!f->sparse_canon || !f->sparse_target)))
+      return VD_EINVAL;
+    if (f->mem != VD_MEM_HOST && f->mem != VD_MEM_DEVICE) return VD_EINVAL;
+    const int C = (int)f->n_model, S = (int)f->n_sparse;
+    const size_t npix = (size_t)cam.W * cam.H;
+    VD_CHECK(ensure_staging(C, S));
+    VD_CHECK(ensure_track(C, S, npix));
+    const hipMemcpyKind kind = f->mem == VD_MEM_HOST ? hipMemcpyHostToDevice
+                                                     : hipMemcpyDeviceToDevice;
+    VD_TRY(hipMemcpyAsync(depth_, f->depth, 4 * npix, kind, stream_));
+    if (C > 0) {
+      VD_TRY(hipMemcpyAsync(st_canon_, f->model_canon, 12ull * C, kind, stream_));
+      VD_TRY(hipMemcpyAsync(st_mnormal_, f->model_normal, 12ull * C, kind, stream_));
+    }
+    if (S > 0) {
+      VD_TRY(hipMemcpyAsync(st_scanon_, f->sparse_canon, 12ull * S, kind, stream_));
+      VD_TRY(hipMemcpyAsync(st_stcam_, f->sparse_target, 12ull * S, kind, stream_));
+    }
+    // validation: finite values, canonical points inside the coarsest level
+    RawConstraints chk;
+    chk.canon = st_canon_; chk.target = st_canon_; chk.normal = st_mnormal_; chk.weight = nullptr;
+    chk.sparse_canon = st_scanon_; chk.sparse_target = st_stcam_;
+    chk.n_dense = C; chk.n_sparse = S;
+    VD_TRY(hipMemsetAsync(d_flags_, 0, sizeof(int), stream_));
+    const LevelData<T>& c0 = lv_[0];
+    VD_TRY(launch_validate(chk, c0.nx, c0.ny, c0.nz, c0.h, desc_.origin, d_flags_, stream_));
+    VD_TRY(launch_check_finite(depth_, (int64_t)npix, d_flags_, stream_));
+    VD_TRY(hipMemcpyAsync(h_flags_, d_flags_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    if (h_flags_[0] & 1) return VD_EINVAL;
+    if (h_flags_[0] & 2) return VD_ERANGE;
+    // the row structure of the model samples, with zero weights until the
+    // first association fills them
+    VD_TRY(launch_fill_float(st_target_, 3ll * C, 0.0f, stream_));
+    VD_TRY(launch_fill_float(st_normal_, 3ll * C, 0.0f, stream_));
+    VD_TRY(launch_fill_float(st_weight_, (int64_t)C, 0.0f, stream_));
+    if (S > 0) VD_TRY(launch_to_model_frame(pose_d_, st_stcam_, st_starget_, S, stream_));
+    cam_ = cam;
+    n_model_ = C;
+    n_fsparse_ = S;
+    VD_CHECK(build_levels(track_raw(), C, S, true));
+    have_frame_ = true;
+    return VD_OK;
+  }
+
+  int get_pose(double* pose) override {
+    if (!pose) return VD_EINVAL;
+    VD_TRY(hipMemcpyAsync(h_pose_, pose_d_, 12 * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    std::memcpy(pose, h_pose_, 12 * sizeof(double));
+    return VD_OK;
+  }
+
+  int set_pose(const double* pose) override {
+    if (!pose) return VD_EINVAL;
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(pose[k])) return VD_EINVAL;
+    VD_TRY(hipStreamSynchronize(stream_));
+    std::memcpy(h_pose_, pose, 12 * sizeof(double));
+    VD_TRY(hipMemcpyAsync(pose_d_, h_pose_, 12 * sizeof(double), hipMemcpyHostToDevice, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  int track_frame(const vd_track_opts* o, vd_track_report* rep) override {
+    if (!o) return VD_EINVAL;
+    if (!have_frame_) return VD_ESTATE;
+    if (o->rigid_iters < 0 || o->rigid_iters > VD_TRACK_MAX_ITERS || o->icp_iters < 0 ||
+        o->icp_iters > VD_TRACK_MAX_ITERS)
+      return VD_EINVAL;
+    LevelData<T>& F = finest();
+    const LevelView<T> FV = F.view(desc_.w_arap);
+    if (o->reset_to_rest) VD_TRY(launch_set_rest<T>(nodes_of(FV), stream_));
+    VD_TRY(launch_fill_int(kept_d_, VD_TRACK_MAX_ITERS, 0, stream_));
+    const ModelView<T> mv = model_view(F.d, F.rot);
+    const int G = rigid_blocks(n_model_);
+    for (int it = 0; it < o->rigid_iters; ++it) {
+      VD_TRY(launch_rigid_reduce_lattice<T>(cam_, depth_, mv, pose_d_, rigid_part_, G, stream_));
+      VD_TRY(launch_rigid_solve(rigid_part_, G, pose_d_, rhist_d_ + 2 * it, stream_));
+    }
+    if (n_fsparse_ > 0)
+      VD_TRY(launch_to_model_frame(pose_d_, st_stcam_, st_starget_, n_fsparse_, stream_));
+    for (int it = 0; it < o->icp_iters; ++it) {
+      VD_TRY(launch_assoc_lattice<T>(cam_, depth_, mv, pose_d_, st_target_, st_normal_,
+                                     st_weight_, nullptr, kept_d_ + it, stream_));
+      VD_CHECK(build_levels(track_raw(), n_model_, n_fsparse_, false));
+      if (desc_.flags & VD_FLAG_GRAPH) {
+        VD_CHECK(run_graph(0));
+      } else {
+        VD_CHECK(enqueue_frame(0, stream_));
+      }
+    }
+    energy_fresh_ = o->icp_iters > 0;
+    if (!rep) return VD_OK;
+    std::memset(rep, 0, sizeof(*rep));
+    if (!energy_fresh_) {
+      VD_TRY(launch_energy<T>(energy_of(FV), one_of(FV), 0, stream_));
+      energy_fresh_ = true;
+    }
+    VD_TRY(hipStreamSynchronize(stream_));
+    VD_TRY(hipMemcpy(h_pose_, pose_d_, 12 * sizeof(double), hipMemcpyDeviceToHost));
+    std::memcpy(rep->pose, h_pose_, sizeof(rep->pose));
+    if (o->rigid_iters > 0)
+      VD_TRY(hipMemcpy(rep->rigid_hist, rhist_d_, 2 * o->rigid_iters * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    VD_TRY(hipMemcpy(rep->assoc_kept, kept_d_, VD_TRACK_MAX_ITERS * sizeof(int),
+                     hipMemcpyDeviceToHost));
+    for (int l = 0; l < L_; ++l) {
+      VD_TRY(hipMemcpy(h_sc_, lv_[l].sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+      if (h_sc_->guard_hits) rep->bits |= VD_REPORT_PCG_GUARD;
+      if (h_sc_->bar_timeouts) rep->bits |= VD_REPORT_BARRIER_TIMEOUT;
+      if (h_sc_->polar_fp64) rep->bits |= VD_REPORT_POLAR_FP64;
+      if (h_sc_->polar_keep) rep->bits |= VD_REPORT_POLAR_KEEP;
+      if (l == L_ - 1)
+        for (int k = 0; k < 4; ++k) rep->energy[k] = h_sc_->energy[k];
+    }
+    return VD_OK;
+  }
+
+  int debug_associate(const float* disp, const float* rot, float* target, float* normal,
+                      float* weight, int* pixel, int mem) override {
+    if (!disp || !rot || !target || !normal || !weight) return VD_EINVAL;
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    if (!have_frame_) return VD_ESTATE;
+    VD_CHECK(ensure_debug());
+    LevelData<T>& F = finest();
+    const size_t N = F.N, M = n_model_;
+    const hipMemcpyKind up = mem == VD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    VD_TRY(hipMemcpyAsync(dbg_f_, disp, 12 * N, up, stream_));
+    VD_TRY(launch_aos_to_soa<T>(dbg_f_, dbg_t1_, (int)N, 3, stream_));
+    VD_TRY(hipMemcpyAsync(dbg_f_, rot, 36 * N, up, stream_));
+    VD_TRY(launch_aos_to_soa<T>(dbg_f_, dbg_rot_, (int)N, 9, stream_));
+    float *t = target, *n = normal, *w = weight;
+    int* px = pixel;
+    if (mem == VD_MEM_HOST) {
+      if (M > dbg_assoc_cap_) {
+        VD_TRY(hipStreamSynchronize(stream_));
+        pool_.release(dbg_assoc_);
+        VD_CHECK(pool_.alloc(&dbg_assoc_, 8 * M));
+        dbg_assoc_cap_ = M;
+      }
+      t = dbg_assoc_;
+      n = dbg_assoc_ + 3 * M;
+      w = dbg_assoc_ + 6 * M;
+      px = pixel ? (int*)(dbg_assoc_ + 7 * M) : nullptr;
+    }
+    VD_TRY(launch_assoc_lattice<T>(cam_, depth_, model_view(dbg_t1_, dbg_rot_), pose_d_, t, n, w,
+                                   px, nullptr, stream_));
+    if (mem == VD_MEM_HOST && M > 0) {
+      VD_TRY(hipMemcpyAsync(target, t, 12 * M, hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipMemcpyAsync(normal, n, 12 * M, hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipMemcpyAsync(weight, w, 4 * M, hipMemcpyDeviceToHost, stream_));
+      if (pixel) VD_TRY(hipMemcpyAsync(pixel, px, 4 * M, hipMemcpyDeviceToHost, stream_));
+    }
+    VD_TRY(hipStreamSynchronize(stream_));
     return VD_OK;
   }
 
@@ -1003,6 +1209,54 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
+  ModelView<T> model_view(const T* d, const T* rot) {
+    const LevelData<T>& F = finest();
+    ModelView<T> m;
+    m.canon = st_canon_; m.cnormal = st_mnormal_; m.M = n_model_;
+    m.d = d; m.rot = rot;
+    m.nx = F.nx; m.ny = F.ny; m.nz = F.nz; m.N = F.N;
+    m.h = F.h; m.ox = desc_.origin[0]; m.oy = desc_.origin[1]; m.oz = desc_.origin[2];
+    return m;
+  }
+
+  // The frame's rows: model samples with the association's targets,
+  // normals and weights, and the sparse pairs in the lattice frame.
+  RawConstraints track_raw() const {
+    RawConstraints r;
+    r.canon = st_canon_; r.target = st_target_; r.normal = st_normal_; r.weight = st_weight_;
+    r.sparse_canon = st_scanon_; r.sparse_target = st_starget_;
+    r.n_dense = n_model_; r.n_sparse = n_fsparse_;
+    return r;
+  }
+
+  int ensure_track(int C, int S, size_t npix) {
+    if (!pose_d_) {
+      VD_CHECK(pool_.alloc(&pose_d_, 12));
+      VD_CHECK(pool_.alloc(&rigid_part_, (size_t)kRigidStride * kRigidMaxBlocks));
+      VD_CHECK(pool_.alloc(&rhist_d_, 2 * VD_TRACK_MAX_ITERS));
+      VD_CHECK(pool_.alloc(&kept_d_, VD_TRACK_MAX_ITERS));
+    }
+    if (C > cap_mnormal_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(st_mnormal_);
+      VD_CHECK(pool_.alloc(&st_mnormal_, 3 * (size_t)cap_dense_));
+      cap_mnormal_ = cap_dense_;
+    }
+    if (S > cap_stcam_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(st_stcam_);
+      VD_CHECK(pool_.alloc(&st_stcam_, 3 * (size_t)cap_sparse_));
+      cap_stcam_ = cap_sparse_;
+    }
+    if (npix > depth_cap_) {
+      VD_TRY(hipStreamSynchronize(stream_));
+      pool_.release(depth_);
+      VD_CHECK(pool_.alloc(&depth_, npix));
+      depth_cap_ = npix;
+    }
+    return VD_OK;
+  }
+
   int upload_aos(const float* src, size_t n, int mem) {
     if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
     VD_TRY(hipMemcpyAsync(dbg_f_, src, n * sizeof(float),
@@ -1079,6 +1333,22 @@ class Solver final : public ISolver {
   float* feat_scratch_ = nullptr;  // per-row residual pieces of the features
   size_t feat_cap_ = 0;
   uint16_t* feat_x_ = nullptr;     // features staged for a host copy
+  // tracking (vd_track.h)
+  CamAssoc cam_{};
+  float* depth_ = nullptr;        // the frame's depth map
+  size_t depth_cap_ = 0;
+  float* st_mnormal_ = nullptr;   // canonical model normals
+  float* st_stcam_ = nullptr;     // camera-frame sparse targets
+  int cap_mnormal_ = 0, cap_stcam_ = 0;
+  int n_model_ = 0, n_fsparse_ = 0;
+  bool have_frame_ = false;
+  double* pose_d_ = nullptr;      // global pose (R row-major, t), float64
+  double* h_pose_ = nullptr;      // pinned host copy
+  double* rigid_part_ = nullptr;  // rigid ICP workgroup partials
+  double* rhist_d_ = nullptr;     // per rigid iteration: E, kept pairs
+  int* kept_d_ = nullptr;         // kept pairs per association round
+  float* dbg_assoc_ = nullptr;    // host-bound association outputs (test entry)
+  size_t dbg_assoc_cap_ = 0;
 };
 
 // ===========================================================================
@@ -1088,7 +1358,10 @@ class Solver final : public ISolver {
 class IBatch {
  public:
   virtual ~IBatch() {}
-  virtual int solve(const vd_solve_opts* o, double* energies) = 0;
+  // Queue one frame of every lattice on `s` (graph replay or eager).
+  virtual int launch(const vd_solve_opts* o, hipStream_t s) = 0;
+  // Final energies (4 per lattice) after the frame finished.
+  virtual int energies(double* e) = 0;
   virtual int profile(double* us, int* n) = 0;
 };
 
@@ -1128,7 +1401,7 @@ class Batch final : public IBatch {
     return VD_OK;
   }
 
-  int solve(const vd_solve_opts* o, double* energies) override {
+  int launch(const vd_solve_opts* o, hipStream_t s) override {
     if (o && (o->init_delta || o->energy_target != 0.0)) return VD_EINVAL;  // single-lattice only
     for (auto* h : h_)
       if (!h->has_constraints()) return VD_ESTATE;
@@ -1160,15 +1433,16 @@ class Batch final : public IBatch {
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) return VD_EHIP;
       }
-      VD_TRY(hipGraphLaunch(exec_[reset], stream_));
+      VD_TRY(hipGraphLaunch(exec_[reset], s));
     } else {
-      VD_CHECK(enqueue(reset, stream_));
+      VD_CHECK(enqueue(reset, s));
     }
     for (auto* h : h_) h->mark_energy_fresh();
-    if (energies) {
-      VD_TRY(hipStreamSynchronize(stream_));
-      for (int b = 0; b < n_; ++b) VD_CHECK(h_[b]->finest_energy_host(energies + 4 * b));
-    }
+    return VD_OK;
+  }
+
+  int energies(double* e) override {
+    for (int b = 0; b < n_; ++b) VD_CHECK(h_[b]->finest_energy_host(e + 4 * b));
     return VD_OK;
   }
 
@@ -1280,27 +1554,29 @@ struct vd_lattice {
   vd::ISolver* impl;
 };
 
+// A batch holds up to two single-precision batches: the float32 lattices
+// (part 0) and the float64 ones (part 1), each with the caller's positions of
+// its lattices.  Part 1 runs on a library-owned stream, forked from and
+// joined back into the lattices' stream, so both overlap on the GPU.
 struct vd_batch {
-  vd::IBatch* impl;
+  vd::IBatch* part[2] = {nullptr, nullptr};
+  std::vector<int> index[2];
+  hipStream_t stream = nullptr;  // the lattices' stream
+  hipStream_t side = nullptr;    // part 1 when both parts exist
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~vd_batch() {
+    delete part[0];
+    delete part[1];
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace {
 
 template <typename S>
-int make_batch(vd_lattice* const* ls, int n, vd_batch** out) {
-  std::vector<S*> hs;
-  for (int b = 0; b < n; ++b) {
-    S* p = dynamic_cast<S*>(ls[b]->impl);
-    if (!p) return VD_EINVAL;  // mixed precisions
-    hs.push_back(p);
-  }
-  const vd_lattice_desc& d0 = hs[0]->desc();
-  for (S* p : hs) {
-    const vd_lattice_desc& d = p->desc();
-    if (d.num_levels != d0.num_levels || p->stream() != hs[0]->stream()) return VD_EINVAL;
-    for (int l = 0; l < d0.num_levels; ++l)
-      if (d.gn_iters[l] != d0.gn_iters[l] || d.pcg_iters[l] != d0.pcg_iters[l]) return VD_EINVAL;
-  }
+int make_part(const std::vector<S*>& hs, vd::IBatch** out) {
   using T = std::remove_pointer_t<decltype(hs[0]->level_view(0).d)>;
   auto* bt = new (std::nothrow) vd::Batch<T>(hs);
   if (!bt) return VD_ENOMEM;
@@ -1309,12 +1585,61 @@ int make_batch(vd_lattice* const* ls, int n, vd_batch** out) {
     delete bt;
     return rc;
   }
+  *out = bt;
+  return VD_OK;
+}
+
+int make_batch(vd_lattice* const* ls, int n, vd_batch** out) {
+  std::vector<vd::Solver<float>*> h32;
+  std::vector<vd::Solver<double>*> h64;
   vd_batch* h = new (std::nothrow) vd_batch;
-  if (!h) {
-    delete bt;
-    return VD_ENOMEM;
+  if (!h) return VD_ENOMEM;
+  const vd_lattice_desc* d0 = nullptr;
+  void* s0 = nullptr;
+  for (int b = 0; b < n; ++b) {
+    const vd_lattice_desc* d;
+    void* st;
+    if (auto* p = dynamic_cast<vd::Solver<float>*>(ls[b]->impl)) {
+      h32.push_back(p);
+      h->index[0].push_back(b);
+      d = &p->desc();
+      st = (void*)p->stream();
+    } else if (auto* q = dynamic_cast<vd::Solver<double>*>(ls[b]->impl)) {
+      h64.push_back(q);
+      h->index[1].push_back(b);
+      d = &q->desc();
+      st = (void*)q->stream();
+    } else {
+      delete h;
+      return VD_EINVAL;
+    }
+    if (!d0) {
+      d0 = d;
+      s0 = st;
+    }
+    bool same = d->num_levels == d0->num_levels && st == s0 &&
+                ((d->flags ^ d0->flags) & VD_FLAG_GRAPH) == 0;
+    for (int l = 0; l < d0->num_levels && same; ++l)
+      same = d->gn_iters[l] == d0->gn_iters[l] && d->pcg_iters[l] == d0->pcg_iters[l];
+    if (!same) {
+      delete h;
+      return VD_EINVAL;
+    }
   }
-  h->impl = bt;
+  h->stream = (hipStream_t)s0;
+  int rc = VD_OK;
+  if (!h32.empty()) rc = make_part(h32, &h->part[0]);
+  if (rc == VD_OK && !h64.empty()) rc = make_part(h64, &h->part[1]);
+  if (rc == VD_OK && h->part[0] && h->part[1]) {
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess)
+      rc = VD_EHIP;
+  }
+  if (rc != VD_OK) {
+    delete h;
+    return rc;
+  }
   *out = h;
   return VD_OK;
 }
@@ -1380,24 +1705,48 @@ int vd_batch_create(vd_lattice* const* ls, int32_t n, vd_batch** out) {
   *out = nullptr;
   for (int b = 0; b < n; ++b)
     if (!ls[b] || !ls[b]->impl) return VD_EINVAL;
-  if (dynamic_cast<vd::Solver<float>*>(ls[0]->impl))
-    return make_batch<vd::Solver<float>>(ls, n, out);
-  return make_batch<vd::Solver<double>>(ls, n, out);
+  return make_batch(ls, n, out);
 }
 
 int vd_batch_solve(vd_batch* b, const vd_solve_opts* o, double* energies) {
   if (!b) return VD_EINVAL;
-  return b->impl->solve(o, energies);
+  if (o && (o->init_delta || o->energy_target != 0.0)) return VD_EINVAL;
+  if (b->part[0] && b->part[1]) {
+    if (hipEventRecord(b->fork, b->stream) != hipSuccess ||
+        hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess)
+      return VD_EHIP;
+    int rc = b->part[1]->launch(o, b->side);
+    if (rc != VD_OK) return rc;
+    rc = b->part[0]->launch(o, b->stream);
+    if (rc != VD_OK) return rc;
+    if (hipEventRecord(b->join, b->side) != hipSuccess ||
+        hipStreamWaitEvent(b->stream, b->join, 0) != hipSuccess)
+      return VD_EHIP;
+  } else {
+    const int rc = (b->part[0] ? b->part[0] : b->part[1])->launch(o, b->stream);
+    if (rc != VD_OK) return rc;
+  }
+  if (!energies) return VD_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return VD_EHIP;
+  std::vector<double> e;
+  for (int k = 0; k < 2; ++k) {
+    if (!b->part[k]) continue;
+    e.assign(4 * b->index[k].size(), 0.0);
+    const int rc = b->part[k]->energies(e.data());
+    if (rc != VD_OK) return rc;
+    for (size_t j = 0; j < b->index[k].size(); ++j)
+      for (int q = 0; q < 4; ++q) energies[4 * b->index[k][j] + q] = e[4 * j + q];
+  }
+  return VD_OK;
 }
 
 int vd_batch_profile(vd_batch* b, double* prof_us, int32_t* prof_n) {
   if (!b || !prof_us || !prof_n) return VD_EINVAL;
-  return b->impl->profile(prof_us, prof_n);
+  return (b->part[0] ? b->part[0] : b->part[1])->profile(prof_us, prof_n);
 }
 
 int vd_batch_destroy(vd_batch* b) {
   if (!b) return VD_OK;
-  delete b->impl;
   delete b;
   return VD_OK;
 }
@@ -1531,6 +1880,160 @@ int vd_debug_fit_rotations(const float* M, const float* R_prev, float* R, int32_
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   return e == hipSuccess ? VD_OK : VD_EHIP;
+}
+
+}  // extern "C"
+
+// ---- tracking (vd_track.h) -------------------------------------------------
+
+namespace {
+
+int camera_check(const vd_camera* c, const vd_assoc_params* a, vd::CamAssoc* out) {
+  return vd::camera_of(c, a, out);
+}
+
+// Device buffers of a synchronous stateless call, freed on scope exit.
+struct Scratch {
+  std::vector<void*> bufs;
+  ~Scratch() {
+    for (void* b : bufs) (void)hipFree(b);
+  }
+  template <typename P>
+  P* get(size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, (count ? count : 1) * sizeof(P)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    bufs.push_back(q);
+    return static_cast<P*>(q);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int vd_associate(const vd_camera* cam, const float* depth, const float* points,
+                 const float* normals, int64_t n, const vd_assoc_params* prm, float* target,
+                 float* normal_out, float* weight, int32_t* pixel, int32_t mem, void* stream) {
+  vd::CamAssoc c;
+  const int rc = camera_check(cam, prm, &c);
+  if (rc != VD_OK) return rc;
+  if (n < 0 || n > (1ll << 30) || !depth) return VD_EINVAL;
+  if (n > 0 && (!points || !normals || !target || !normal_out || !weight)) return VD_EINVAL;
+  if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+  if (n == 0) return VD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t npix = (size_t)c.W * c.H;
+  const float *dd = depth, *dp = points, *dn = normals;
+  float *dt = target, *dno = normal_out, *dw = weight;
+  int* dpx = pixel;
+  Scratch sc;
+  if (mem == VD_MEM_HOST) {
+    float* b = sc.get<float>(npix + 13 * (size_t)n);
+    int* bp = pixel ? sc.get<int>((size_t)n) : nullptr;
+    if (!b || (pixel && !bp)) return VD_ENOMEM;
+    float* q = b;
+    if (hipMemcpyAsync(q, depth, 4 * npix, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(q + npix, points, 12 * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(q + npix + 3 * n, normals, 12 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+      return VD_EHIP;
+    dd = q;
+    dp = q + npix;
+    dn = q + npix + 3 * n;
+    dt = q + npix + 6 * n;
+    dno = q + npix + 9 * n;
+    dw = q + npix + 12 * n;
+    dpx = bp;
+  }
+  if (vd::launch_associate(c, dd, dp, dn, (int)n, dt, dno, dw, dpx, s) != hipSuccess)
+    return VD_EHIP;
+  if (mem == VD_MEM_HOST) {
+    if (hipMemcpyAsync(target, dt, 12 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(normal_out, dno, 12 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(weight, dw, 4 * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (pixel && hipMemcpyAsync(pixel, dpx, 4 * n, hipMemcpyDeviceToHost, s) != hipSuccess))
+      return VD_EHIP;
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? VD_OK : VD_EHIP;
+}
+
+int vd_rigid_pose(const vd_camera* cam, const float* depth, const float* points,
+                  const float* normals, int64_t n, const vd_assoc_params* prm, int32_t iters,
+                  double* pose, double* hist, int32_t mem, void* stream) {
+  vd::CamAssoc c;
+  const int rc = camera_check(cam, prm, &c);
+  if (rc != VD_OK) return rc;
+  if (n < 0 || n > (1ll << 30) || iters < 0 || !depth || !pose) return VD_EINVAL;
+  if (n > 0 && (!points || !normals)) return VD_EINVAL;
+  if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+  if (mem == VD_MEM_HOST)
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(pose[k])) return VD_EINVAL;
+  if (iters == 0) return VD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t npix = (size_t)c.W * c.H;
+  const int G = vd::rigid_blocks(n);
+  Scratch sc;
+  double* part = sc.get<double>((size_t)vd::kRigidStride * G);
+  if (!part) return VD_ENOMEM;
+  const float *dd = depth, *dp = points, *dn = normals;
+  double *dpose = pose, *dhist = hist;
+  if (mem == VD_MEM_HOST) {
+    float* b = sc.get<float>(npix + 6 * (size_t)n);
+    double* pb = sc.get<double>(12 + 2 * (size_t)iters);
+    if (!b || !pb) return VD_ENOMEM;
+    if (hipMemcpyAsync(b, depth, 4 * npix, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (n > 0 && hipMemcpyAsync(b + npix, points, 12 * n, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (n > 0 &&
+         hipMemcpyAsync(b + npix + 3 * n, normals, 12 * n, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemcpyAsync(pb, pose, 12 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      return VD_EHIP;
+    dd = b;
+    dp = b + npix;
+    dn = b + npix + 3 * n;
+    dpose = pb;
+    dhist = hist ? pb + 12 : nullptr;
+  }
+  for (int it = 0; it < iters; ++it) {
+    if (vd::launch_rigid_reduce_points(c, dd, dp, dn, (int)n, dpose, part, G, s) != hipSuccess ||
+        vd::launch_rigid_solve(part, G, dpose, dhist ? dhist + 2 * it : nullptr, s) != hipSuccess)
+      return VD_EHIP;
+  }
+  if (mem == VD_MEM_HOST) {
+    if (hipMemcpyAsync(pose, dpose, 12 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (hist && hipMemcpyAsync(hist, dhist, 2 * iters * sizeof(double), hipMemcpyDeviceToHost,
+                                s) != hipSuccess))
+      return VD_EHIP;
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? VD_OK : VD_EHIP;
+}
+
+int vd_set_depth_frame(vd_lattice* l, const vd_depth_frame* f) {
+  if (!l) return VD_EINVAL;
+  return l->impl->set_depth_frame(f);
+}
+
+int vd_get_pose(vd_lattice* l, double pose[12]) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_pose(pose);
+}
+
+int vd_set_pose(vd_lattice* l, const double pose[12]) {
+  if (!l) return VD_EINVAL;
+  return l->impl->set_pose(pose);
+}
+
+int vd_track_frame(vd_lattice* l, const vd_track_opts* o, vd_track_report* r) {
+  if (!l) return VD_EINVAL;
+  return l->impl->track_frame(o, r);
+}
+
+int vd_debug_associate(vd_lattice* l, const float* disp, const float* rot, float* target,
+                       float* normal_out, float* weight, int32_t* pixel, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->debug_associate(disp, rot, target, normal_out, weight, pixel, mem);
 }
 
 }  // extern "C"

@@ -381,14 +381,18 @@ __global__ void k_mse_finalize(const double* part, int n, double inv_m, double* 
   if (threadIdx.x == 0) *loss = s * inv_m;
 }
 
+// One Adam step.  ob1 = 1 - beta1 and ob2 = 1 - beta2 arrive rounded from
+// their float64 values: 1.f - 0.999f would lose four digits to cancellation
+// (a 1.3e-5 relative error in every second-moment update).
 __global__ __launch_bounds__(kBlock) void k_adam(float* p, const float* __restrict__ g, float* m1,
-                                                 float* m2, int64_t n, float lr, float b1, float b2,
-                                                 float eps, float c1, float c2) {
+                                                 float* m2, int64_t n, float lr, float b1,
+                                                 float ob1, float b2, float ob2, float eps,
+                                                 float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float a = b1 * m1[i] + (1.f - b1) * gi;
-  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  const float a = b1 * m1[i] + ob1 * gi;
+  const float b = b2 * m2[i] + ob2 * gi * gi;
   m1[i] = a;
   m2[i] = b;
   p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
@@ -684,13 +688,14 @@ class Net {
 
   int adam(float lr) {
     ++step_;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)step_));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)step_));
+    const double b1 = 0.9, b2 = 0.999;
+    const float eps = 1e-8f;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)step_));
+    const float c2 = (float)(1.0 - std::pow(b2, (double)step_));
     const int64_t P = param_count();
-    k_adam<<<(unsigned)((P + kBlock - 1) / kBlock), kBlock, 0, stream_>>>(params_, grad_, m1_, m2_,
-                                                                         P, lr, b1, b2, eps, c1,
-                                                                         c2);
+    k_adam<<<(unsigned)((P + kBlock - 1) / kBlock), kBlock, 0, stream_>>>(
+        params_, grad_, m1_, m2_, P, lr, (float)b1, (float)(1.0 - b1), (float)b2,
+        (float)(1.0 - b2), eps, c1, c2);
     if (hipGetLastError() != hipSuccess) return VD_EHIP;
     return pack() == hipSuccess ? VD_OK : VD_EHIP;
   }

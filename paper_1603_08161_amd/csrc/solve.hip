@@ -422,8 +422,26 @@ hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, 
 // halo inputs are loaded before the scalar reduction so that both latencies
 // overlap.  The last iteration's step is applied by k_cg_final.
 
+// A CG scalar as the sum hi + lo of two T values (lo = 0 for float64).  The
+// step sizes are computed in float64 and applied to float32 vectors through
+// both parts, x + s y = fma(lo, y, fma(hi, y, x)): a step size rounded to
+// float32 would perturb the iterate coherently along p, and truncated CG
+// amplifies such perturbations by about an order of magnitude per iteration
+// once its Ritz values settle.
+template <typename T>
+struct Step {
+  T hi, lo;
+  __device__ __forceinline__ static Step of(double s) {
+    Step r;
+    r.hi = (T)s;
+    r.lo = (T)(s - (double)r.hi);
+    return r;
+  }
+  __device__ __forceinline__ T axpy(T x, T y) const { return fma(lo, y, fma(hi, y, x)); }
+};
+
 template <typename T, int NT = kBlock>
-__device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& beta,
+__device__ __forceinline__ void cg_scalars(const double* s, int n, Step<T>& alpha, Step<T>& beta,
                                            Scalars* sc, bool count_guard) {
   double v[4];
   sum_partials_k<4, NT>(s, n, v);
@@ -431,8 +449,8 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, T& alpha, T& 
   const double a = pap > 0.0 ? rz / pap : 0.0;
   double rz_new = rz - 2.0 * a * apdr + a * a * apdap;
   if (rz_new < 0.0) rz_new = 0.0;
-  alpha = (T)a;
-  beta = rz > 0.0 ? (T)(rz_new / rz) : T(0);
+  alpha = Step<T>::of(a);
+  beta = Step<T>::of(rz > 0.0 ? rz_new / rz : 0.0);
   if (count_guard && threadIdx.x == 0 && !(pap > 0.0)) sc->guard_hits += 1;
 }
 
@@ -523,7 +541,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     }
   }
   // 2. CG scalars of the previous iterate
-  T alpha = T(0), beta = T(0);
+  Step<T> alpha = Step<T>::of(0.0), beta = Step<T>::of(0.0);
   if (!FIRST) cg_scalars<T, TL::NT>(s_in, L.ntiles, alpha, beta, L.sc, w.local == 0);
   int rank[TL::NPT];
   list_data_nodes<T, TL>(own_slot, ds, rank);
@@ -536,9 +554,9 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       T r = hr[h][a];
-      if (!FIRST) r -= alpha * ha[h][a];
+      if (!FIRST) r = alpha.axpy(r, -ha[h][a]);
       T p = hq[h][a] * r;
-      if (!FIRST) p += beta * hp[h][a];
+      if (!FIRST) p = beta.axpy(p, hp[h][a]);
       r3[a] = r;
       p3[a] = p;
       sp[a][k] = p;
@@ -553,7 +571,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
         p_out[j] = p3[a];
         if (!FIRST) {
           r_out[j] = r3[a];
-          if (!PF) L.d[j] += alpha * hp[h][a];
+          if (!PF) L.d[j] = alpha.axpy(L.d[j], hp[h][a]);
         }
       }
     }
@@ -578,7 +596,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       if (rank[kk] >= 0) o[a] += ds.d[a][e];
       const size_t j = a * N + i;
       ap_out[j] = o[a];
-      if (!FIRST && PF) L.d[j] = own_d[kk][a] + alpha * own_pp[kk][a];
+      if (!FIRST && PF) L.d[j] = alpha.axpy(own_d[kk][a], own_pp[kk][a]);
       const double q = (double)(PF ? own_q[kk][a] : dinv[j]), r = (double)sr[a][c],
                    p = (double)sp[a][c];
       const double ap = (double)o[a];
@@ -656,7 +674,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const bool odd = (last & 1) != 0;
-  T alpha, beta;
+  Step<T> alpha, beta;
   cg_scalars<T, TL::NT>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
   const size_t N = L.N;
   const T* __restrict__ p = odd ? L.pb : L.pa;
@@ -669,7 +687,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) d[a * N + i] += alpha * p[a * N + i];
+    for (int a = 0; a < 3; ++a) d[a * N + i] = alpha.axpy(d[a * N + i], p[a * N + i]);
   }
 }
 
@@ -699,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
   const bool odd = (last & 1) != 0;
-  T alpha, beta;
+  Step<T> alpha, beta;
   cg_scalars<T>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
   const int i = w.local * kBlock + threadIdx.x;
   if (i >= L.N) return;
@@ -707,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
   const T* __restrict__ p = odd ? L.pb : L.pa;
   T* __restrict__ d = L.d;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) d[a * N + i] += alpha * p[a * N + i];
+  for (int a = 0; a < 3; ++a) d[a * N + i] = alpha.axpy(d[a * N + i], p[a * N + i]);
 }
 
 template <typename T, typename TL>

@@ -12,7 +12,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vd.h")
-HEADERS = [HEADER, os.path.join(ROOT, "include", "vd_net.h")]
+HEADERS = [HEADER, os.path.join(ROOT, "include", "vd_net.h"),
+           os.path.join(ROOT, "include", "vd_track.h")]
 
 
 def _declared():

@@ -90,7 +90,27 @@ def test_batch_rejects_mismatched_handles():
     with pytest.raises(VDError) as ei:
         Batch([a, b])
     assert ei.value.code == VD_EINVAL
-    c = make_lattice(scenes[1], precision="fp64")
+    c = make_lattice(scenes[1], graph=True)  # other launch mode
     with pytest.raises(VDError) as ei:
         Batch([a, c])
     assert ei.value.code == VD_EINVAL
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_mixed_precision_batch_equals_individual_solves(graph):
+    """float32 and float64 lattices in one batch: two parts, the float64 one
+    on a forked stream; every lattice bitwise equal to its own solve, the
+    energies returned in the caller's order."""
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes(gn=2, pcg=6)
+    precs = ["fp32", "fp64", "fp32", "fp64", "fp64"]
+    lats = [make_lattice(s, precision=p, graph=graph) for s, p in zip(scenes, precs)]
+    batch = Batch(lats)
+    for frame in range(2):
+        E = batch.solve(reset=(frame == 0), energies=True)
+    for s, p, lat, e in zip(scenes, precs, lats, E):
+        ref = make_lattice(s, precision=p, graph=graph)
+        ref.solve_frame(reset=True)
+        rep = ref.solve_frame(report=True)
+        np.testing.assert_array_equal(e, rep["energy"])
+        np.testing.assert_array_equal(lat.get_state()[0], ref.get_state()[0])
