@@ -173,6 +173,27 @@ int vd_track_frame(vd_lattice* l, const vd_track_opts* o, vd_track_report* repor
 int vd_debug_associate(vd_lattice* l, const float* disp, const float* rot, float* target,
                        float* normal_out, float* weight, int32_t* pixel, int32_t mem);
 
+/* ---- no-allocation entry point ------------------------------------------ */
+
+#define VD_NOALLOC_MAX_SAMPLES (1ll << 30)
+
+/* vd_rigid_pose for callers that cannot allocate device memory: code under
+ * HIP graph capture, serving loops and harnesses that forbid hipMalloc.
+ * Arguments and results as vd_rigid_pose with mem = VD_MEM_DEVICE: every
+ * pointer is device memory of the current GPU, pose[12] is read and updated
+ * in place on the device, hist (may be NULL) receives 2 * iters float64
+ * there.  The reduction's workgroup partials live in a fixed library-owned
+ * device array (256 KiB per GPU, held until the process ends); the call
+ * allocates nothing and does not wait for the GPU.  Every partial a call
+ * reads it has written before in the same call, so nothing has to start at
+ * zero.  Calls that overlap on one GPU share that array and race: serialise
+ * them (one stream, or events).  VD_ERANGE for n > VD_NOALLOC_MAX_SAMPLES;
+ * otherwise VD_EINVAL as vd_rigid_pose (the pose, being device memory, is not
+ * checked for finite values). */
+int vd_rigid_pose_noalloc(const vd_camera* cam, const float* depth, const float* points,
+                          const float* normals, int64_t n, const vd_assoc_params* prm,
+                          int32_t iters, double* pose, double* hist, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     associate,
     batch_precision,
     rigid_pose,
+    rigid_pose_noalloc,
     VDError,
     fit_rotations,
     lib,

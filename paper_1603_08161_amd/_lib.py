@@ -48,9 +48,10 @@ EXPORTED = (
     "vd_get_profile", "vd_warm_features", "vd_net_param_count", "vd_net_create", "vd_net_destroy",
     "vd_net_set_params", "vd_net_get_params", "vd_net_forward", "vd_net_gradients",
     "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
-    "vd_set_pose", "vd_track_frame", "vd_debug_associate",
+    "vd_set_pose", "vd_track_frame", "vd_debug_associate", "vd_rigid_pose_noalloc",
 )
 VD_TRACK_MAX_ITERS = 64
+VD_NOALLOC_MAX_SAMPLES = 1 << 30
 
 
 class LatticeDesc(C.Structure):
@@ -231,6 +232,8 @@ def _load() -> C.CDLL:
         "vd_set_pose": ([vp, dp], C.c_int),
         "vd_track_frame": ([vp, C.POINTER(TrackOpts), C.POINTER(TrackReport)], C.c_int),
         "vd_debug_associate": ([vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
+        "vd_rigid_pose_noalloc": ([C.POINTER(Camera), vp, vp, vp, i64, C.POINTER(AssocParams),
+                                   i32, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -652,6 +655,29 @@ def rigid_pose(cam, depth, points, normals, eps, iters: int, pose=None,
                               p.shape[0], C.byref(a), int(iters), P.ctypes.data,
                               hist.ctypes.data, VD_MEM_HOST, C.c_void_p(s)), "vd_rigid_pose")
     return P, hist[:iters]
+
+
+def rigid_pose_noalloc(cam, depth, points, normals, eps, iters: int, pose, hist=None,
+                       stream: Optional[int] = None) -> None:
+    """vd_rigid_pose_noalloc: every array a contiguous CUDA tensor of the
+    current GPU -- depth (H, W), points and normals (n, 3) float32; pose (12,)
+    float64, updated in place; hist (2 * iters,) float64 or None.  Queued on
+    the stream without waiting."""
+    arrays = (depth, points, normals, pose) + (() if hist is None else (hist,))
+    if not all(_is_device(a) and a.is_contiguous() for a in arrays):
+        raise ValueError("vd_rigid_pose_noalloc takes contiguous device tensors only")
+    if not all(a.dtype == torch.float32 for a in (depth, points, normals)) or \
+            pose.dtype != torch.float64 or (hist is not None and hist.dtype != torch.float64):
+        raise ValueError("depth, points, normals float32; pose and hist float64")
+    if pose.numel() != 12 or (hist is not None and hist.numel() < 2 * iters):
+        raise ValueError("pose needs 12 entries and hist 2 * iters")
+    c, a = _camera(cam), _assoc(eps)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_rigid_pose_noalloc(C.byref(c), depth.data_ptr(), points.data_ptr(),
+                                      normals.data_ptr(), points.shape[0], C.byref(a),
+                                      int(iters), pose.data_ptr(),
+                                      None if hist is None else hist.data_ptr(),
+                                      C.c_void_p(s)), "vd_rigid_pose_noalloc")
 
 
 def batch_precision(n: int) -> str:
