@@ -633,3 +633,49 @@ def make_box_frame(Q=None, c=None, cam: Dict = CAM, step: int = 3, margin: int =
     nrm = np.stack([BOX_PLANES[k][0] for k in label[vv_i, uu_i]])
     return DepthFrame(depth=depth.astype(np.float32), camera=dict(cam),
                       model_canon=pts.astype(np.float32), model_normal=nrm.astype(np.float32))
+
+
+def make_patch(seed: int = 0, dims=(12, 12, 12), spacing: float = 1.0, n_dense: int = 600,
+               n_sparse: int = 12, num_levels: int = 1, gn: int = 3, pcg: int = 10,
+               amp: float = 0.4, extent: float = 0.6, weights=(1.0, 10.0, 5.0)) -> Scene:
+    """A surface patch inside the lattice: samples on a disc of the tilted
+    plane through the lattice centre (radius ``extent`` of the half-span), so
+    that only the cells near the plane hold samples; targets pushed along the
+    plane normal by a smooth bump of amplitude ``amp`` spacings plus noise,
+    normals the plane normal; sparse pairs on the same disc."""
+    rng = np.random.default_rng(seed)
+    dims = tuple(int(d) for d in dims)
+    nc = np.asarray(dims)
+    for _ in range(num_levels - 1):
+        nc = (nc + 1) // 2
+    span = (nc - 1) * spacing * (2 ** (num_levels - 1))
+    centre = 0.5 * span
+    m = np.array([0.3, -0.2, 1.0])
+    m /= np.linalg.norm(m)
+    u = np.cross(m, [1.0, 0.0, 0.0])
+    u /= np.linalg.norm(u)
+    v = np.cross(m, u)
+    rad = extent * 0.5 * float(span.min())
+
+    def disc(k):
+        r = rad * np.sqrt(rng.uniform(size=k))
+        th = rng.uniform(0.0, 2 * np.pi, size=k)
+        return centre + (r * np.cos(th))[:, None] * u + (r * np.sin(th))[:, None] * v
+
+    canon = disc(n_dense)
+    s = (canon - centre) @ u / rad
+    bump = amp * spacing * np.exp(-4.0 * s * s)
+    target = canon + bump[:, None] * m + 0.02 * spacing * rng.normal(size=canon.shape)
+    normal = np.broadcast_to(m, canon.shape)
+    sp_canon = disc(n_sparse)
+    s2 = (sp_canon - centre) @ u / rad
+    sp_target = sp_canon + (amp * spacing * np.exp(-4.0 * s2 * s2))[:, None] * m
+    spec = LatticeSpec(dims=dims, spacing=spacing, origin=(0.0, 0.0, 0.0),
+                       num_levels=num_levels, gn_iters=(gn,) * num_levels,
+                       pcg_iters=(pcg,) * num_levels,
+                       w_dense=weights[0], w_sparse=weights[1], w_arap=weights[2])
+    return Scene(spec=spec, canon=canon.astype(np.float32), target=target.astype(np.float32),
+                 normal=normal.astype(np.float32),
+                 weight=np.ones(n_dense, np.float32), sparse_canon=sp_canon.astype(np.float32),
+                 sparse_target=sp_target.astype(np.float32),
+                 meta={"config": "patch", "seed": seed})
