@@ -13,10 +13,10 @@ field.  Readings where the paper is silent:
     a constraint sample (dense or sparse; the samples are the isosurface's
     samples, whatever their association weight), per level;
   * M2 M = those points plus their 6-neighbourhood (the one-ring, as N_i);
-  * M3 eq. (4) is read literally: i runs over M and j over all of N_i; a
-    neighbour j outside M is not optimised and enters with its stored
-    position (a fixed anchor), and the directed term (j, i) of such a j is
-    not in the sum;
+  * M3 eq. (4) sums over the points used in the optimisation: i runs over M
+    and j over the one-ring points of i that are in M (a point outside M is
+    not used at all, so no term anchors M to its stale position; every
+    isosurface point keeps its whole one-ring, which is why M adds it);
   * M4 points outside M keep their position and rotation through the frame;
     on every level the prolongated increment and the rotation steps act on
     M only;
@@ -29,7 +29,7 @@ field.  Readings where the paper is silent:
     previous M (the first frame) nothing is extrapolated.
 
 Solved as in ``solver.solve_frame``: per level the residual vector of
-eqs. (2)-(4) with the ARAP rows of the directed edges (i, j), i in M; the
+eqs. (2)-(4) with the ARAP rows of the directed edges inside M; the
 position step is Jacobi-PCG (or a direct solve) on the normal equations
 restricted to the coordinates of M.
 """
@@ -75,8 +75,8 @@ def active_set(grid: Grid, cons: Constraints) -> np.ndarray:
 
 
 class ActiveSystem:
-    """J of eqs. (2)-(4) with the ARAP rows of edges (i, j), i in M, and the
-    normal equations restricted to the coordinates of M."""
+    """J of eqs. (2)-(4) with the ARAP rows of the edges (i, j) inside M, and
+    the normal equations restricted to the coordinates of M."""
 
     def __init__(self, grid: Grid, cons: Constraints, act: np.ndarray):
         self.grid, self.act = grid, act
@@ -100,7 +100,7 @@ class ActiveSystem:
                 vals.append(np.full(S, ss) * beta[:, k])
         self.c_sparse = ss * cons.sparse_target.reshape(-1)
         src, dst = arap_edges(grid)
-        keep = act[src]
+        keep = act[src] & act[dst]
         src, dst = src[keep], dst[keep]
         E = src.size
         base = C + 3 * S
@@ -150,7 +150,7 @@ class ActiveSystem:
 def energy_terms_active(grid: Grid, t: np.ndarray, R: np.ndarray, cons: Constraints,
                         act: np.ndarray):
     """(E_total, w_d E_dense, w_s E_sparse, w_r E_reg) with E_reg summed over
-    the directed edges (i, j), i in M (reading M3), from the definitions."""
+    the directed edges inside M (reading M3), from the definitions."""
     ids, alpha = trilinear(grid, cons.canon)
     S_p = np.einsum("ck,cka->ca", alpha, t[ids])
     e_dense = float(np.sum(cons.weight * np.einsum("ca,ca->c", S_p - cons.target,
@@ -159,7 +159,7 @@ def energy_terms_active(grid: Grid, t: np.ndarray, R: np.ndarray, cons: Constrai
     S_f = np.einsum("sk,ska->sa", beta, t[ids_s])
     e_sparse = float(np.sum((S_f - cons.sparse_target) ** 2))
     src, dst = arap_edges(grid)
-    keep = act[src]
+    keep = act[src] & act[dst]
     src, dst = src[keep], dst[keep]
     rest = grid.rest_positions()
     rot_e = np.einsum("eab,eb->ea", R[src], rest[src] - rest[dst])
@@ -169,11 +169,12 @@ def energy_terms_active(grid: Grid, t: np.ndarray, R: np.ndarray, cons: Constrai
 
 
 def rotation_step_active(grid: Grid, t: np.ndarray, R: np.ndarray, act: np.ndarray):
-    """Procrustes fit (Sec. 7.1) of every point of M over its whole one-ring;
-    points outside M keep their rotation."""
+    """Procrustes fit (Sec. 7.1) of every point of M over its one-ring points
+    in M (the terms of eq. (4) that depend on R_i); points outside M keep
+    their rotation."""
     src, dst = arap_edges(grid)
     rest = grid.rest_positions()
-    keep = act[src]
+    keep = act[src] & act[dst]
     src, dst = src[keep], dst[keep]
     M = np.zeros((grid.n, 3, 3))
     np.add.at(M, src, np.einsum("ea,eb->eab", t[src] - t[dst], rest[src] - rest[dst]))
