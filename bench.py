@@ -208,6 +208,7 @@ def main() -> int:
         print(f"# oracle: {t_cpu:.2f} s/frame, E = {e_ref:.9g}", flush=True)
 
     track_leg = tracked_frame_leg(args, tiles)
+    active_leg = active_set_leg(args, scene, inputs)
 
     warm_leg = None
     if not args.no_warm:
@@ -270,10 +271,68 @@ def main() -> int:
         "kernel_mean_us_eager": prof_us,
         "cpu_baseline": out_cpu,
         "tracked_frame": track_leg,
+        "active_set": active_leg,
         "warm_vs_plain": warm_leg,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def active_set_leg(args, scene, inputs):
+    """The same 64^3 frame restricted to the optimised set M of Sec. 6-7
+    (isosurface points plus their one-ring, VD_FLAG_ACTIVE_SET): frames/s of
+    the same timed step, its own autotuned tiles, the oracle gate against the
+    restricted FP64 solve, and the CG iteration's time and model bytes
+    (144 B per point of M + 24 B per dense and 12 B per sparse sample)."""
+    import numpy as np
+    import torch
+
+    from paper_1603_08161_amd import Lattice
+
+    spec = scene.spec
+    lat = Lattice.from_spec(spec, graph=True, profile=True, active_set=True)
+    lat.set_constraints(*inputs)
+    tiles, _ = lat.tune(iters=10)
+    _, n_act, _ = lat.get_active()
+
+    def step():
+        lat.set_constraints(*inputs)
+        lat.solve_frame(reset=True)
+        return lat.get_energy()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    energies = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        energies.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    graph_us, _ = lat.profile()
+    cg_us = float(graph_us["cg_a"])
+    nbytes = 144.0 * n_act + 24.0 * scene.n_dense + 12.0 * scene.n_sparse
+    e_ref = None
+    solved = args.steps
+    rel = None
+    if not args.no_oracle:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import active
+        with threadpool_limits(limits=1):
+            e_ref = float(active.solve_frame_active(scene)["energy"][0])
+        rel = np.abs(np.array(energies)[:, 0] / e_ref - 1.0)
+        solved = int(np.sum(rel <= 1e-4))
+    print(f"# active set M: {n_act} of {spec.dims[0] ** 3} finest points; "
+          f"{elapsed * 1e3 / args.steps:.2f} ms/frame; CG iteration {cg_us:.2f} us; tiles {tiles}",
+          flush=True)
+    return {"workload": "the 64^3 frame optimised on M only (isosurface points + one-ring)",
+            "value": solved / elapsed, "unit": "frames/s", "ms_per_frame": elapsed * 1e3 /
+            args.steps, "solved_frames": solved, "active_points": n_act,
+            "energy_gpu": float(energies[-1][0]), "energy_oracle": e_ref,
+            "max_rel_energy_err": None if rel is None else float(rel.max()),
+            "tiles": tiles, "cg_iteration_us": cg_us, "cg_model_bytes": nbytes,
+            "cg_effective_GBs": nbytes / (cg_us * 1e-6) / 1e9}
 
 
 def tracked_frame_leg(args, tiles, rigid_iters: int = 2, icp_iters: int = 2):
@@ -314,13 +373,29 @@ def tracked_frame_leg(args, tiles, rigid_iters: int = 2, icp_iters: int = 2):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     print(f"# tracked frame: {ms:.2f} ms ({rigid_iters} rigid + {icp_iters} association "
           f"rounds), kept {list(rep['assoc_kept'])} of {frame.model_canon.shape[0]}", flush=True)
+    # fusion of the frame into the canonical TSDF (Sec. 8) and the mesh of
+    # the fused surface (Sec. 4), deformed by the tracked state
+    tau = 3.0 * scene.spec.spacing
+    lat.fuse_depth(tau=tau, all_points=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lat.fuse_depth(tau=tau, all_points=True, count=False)
+    torch.cuda.synchronize()
+    fuse_ms = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    canon, _, _, _ = lat.extract_mesh()
+    mesh_ms = (time.perf_counter() - t0) * 1e3
+    print(f"# fusion {fuse_ms:.3f} ms/frame; marching cubes {mesh_ms:.2f} ms "
+          f"({canon.shape[0]} triangles, host copies included)", flush=True)
     return {"workload": f"64^3 torus frame: {frame.model_canon.shape[0]} model samples, "
                         f"640x480 depth, {scene.n_sparse} sparse pairs; {rigid_iters} rigid ICP "
                         f"iterations + {icp_iters} x (association + 3-level schedule)",
             "ms_per_frame": ms, "frames": steps,
             "assoc_kept": [int(k) for k in rep["assoc_kept"]],
             "rigid_hist": rep["rigid_hist"].tolist(), "energy": float(rep["energy"][0]),
-            "eps": list(TRACK_EPS)}
+            "eps": list(TRACK_EPS), "fusion_ms": fuse_ms, "mesh_ms_with_host_copies": mesh_ms,
+            "mesh_triangles": int(canon.shape[0])}
 
 
 def warm_vs_plain(frames: int, pool=None):

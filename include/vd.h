@@ -77,6 +77,17 @@ extern "C" {
                               solve as one persistent launch with a grid
                               barrier between iterations (default: one launch
                               per CG iteration) */
+#define VD_FLAG_ACTIVE_SET 16u /* optimise only the set M of Sec. 6-7: on each
+                                  level the corners of the cells holding
+                                  samples (the isosurface's points) plus their
+                                  6-neighbours.  E_reg then sums the edges
+                                  inside M (points outside M are not used);
+                                  points outside M keep their state
+                                  through the frame; tiles without points of M
+                                  are skipped.  Each constraint build grows M
+                                  from the previous build's: points that join
+                                  it are initialised by extrapolating the
+                                  field (Sec. 8; see vd_get_active) */
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
@@ -270,6 +281,16 @@ int vd_get_state(vd_lattice* l, float* pos, float* rot, int32_t mem);
 /* Overwrite the finest state (checkpoint / resume).  rot may be NULL (then
  * R = I).  VD_EINVAL on non-finite input. */
 int vd_set_state(vd_lattice* l, const float* pos, const float* rot, int32_t mem);
+
+/* The optimised set M of a level (VD_FLAG_ACTIVE_SET; without it every
+ * point): mask[N] (may be NULL) receives 1 for the points of M, *count (may be
+ * NULL) their number, *growth_layers (may be NULL) the number of layers the
+ * last constraint build extrapolated on the finest level (a point that joins
+ * M takes the mean displacement of its already initialised 6-neighbours and
+ * the rotation of the first of them in the order -x, +x, -y, +y, -z, +z).
+ * Waits for the stream. */
+int vd_get_active(vd_lattice* l, int32_t level, uint8_t* mask, int64_t* count,
+                  int32_t* growth_layers);
 
 /* Node count and dims of a level (0 = coarsest). */
 int vd_level_info(const vd_lattice* l, int32_t level, int32_t dims[3], double* spacing);

@@ -1,5 +1,5 @@
-"""ctypes binding of libvd.so (the C-ABI in include/vd.h, include/vd_net.h and
-include/vd_track.h).
+"""ctypes binding of libvd.so (the C-ABI in include/vd.h, include/vd_net.h,
+include/vd_track.h and include/vd_fusion.h).
 
 Argument marshalling only: every step of the solve runs in the library's HIP
 kernels.  Arrays may be numpy (host memory) or torch CUDA tensors (device
@@ -30,6 +30,7 @@ VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE = 0, -1, -2, -3, -4, 
 VD_FP32_FP64RED, VD_FP64 = 0, 1
 VD_MEM_HOST, VD_MEM_DEVICE = 0, 1
 VD_FLAG_GRAPH, VD_FLAG_TRACE, VD_FLAG_PROFILE, VD_FLAG_PERSIST = 1, 2, 4, 8
+VD_FLAG_ACTIVE_SET = 16
 VD_PROF_KINDS = 8
 PROF_NAMES = ("gradient", "cg_a", "cg_b", "rotation", "energy", "transfer", "cg_loop")
 VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
@@ -49,6 +50,7 @@ EXPORTED = (
     "vd_net_set_params", "vd_net_get_params", "vd_net_forward", "vd_net_gradients",
     "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
     "vd_set_pose", "vd_track_frame", "vd_debug_associate", "vd_rigid_pose_noalloc",
+    "vd_get_active", "vd_fuse_depth", "vd_get_tsdf", "vd_set_tsdf", "vd_extract_mesh",
 )
 VD_TRACK_MAX_ITERS = 64
 VD_NOALLOC_MAX_SAMPLES = 1 << 30
@@ -145,6 +147,15 @@ class DepthFrameC(C.Structure):
     ]
 
 
+class FuseOpts(C.Structure):
+    _fields_ = [
+        ("tau", C.c_double),
+        ("w_max", C.c_double),
+        ("k_min", C.c_int32),
+        ("all_points", C.c_int32),
+    ]
+
+
 class TrackOpts(C.Structure):
     _fields_ = [
         ("rigid_iters", C.c_int32),
@@ -234,6 +245,11 @@ def _load() -> C.CDLL:
         "vd_debug_associate": ([vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "vd_rigid_pose_noalloc": ([C.POINTER(Camera), vp, vp, vp, i64, C.POINTER(AssocParams),
                                    i32, vp, vp, vp], C.c_int),
+        "vd_get_active": ([vp, i32, vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
+        "vd_fuse_depth": ([vp, C.POINTER(FuseOpts), C.POINTER(C.c_int64)], C.c_int),
+        "vd_get_tsdf": ([vp, vp, vp, vp, i32], C.c_int),
+        "vd_set_tsdf": ([vp, vp, vp, i32], C.c_int),
+        "vd_extract_mesh": ([vp, i64, vp, vp, vp, vp, C.POINTER(C.c_int64), i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -304,7 +320,7 @@ class Lattice:
     def __init__(self, dims, spacing, origin, num_levels=1, gn_iters=(5,), pcg_iters=(10,),
                  w_dense=1.0, w_sparse=10.0, w_arap=5.0, precision="fp32",
                  graph=False, trace=False, profile=False, tiles=None, persistent=False,
-                 stream: Optional[int] = None):
+                 active_set=False, stream: Optional[int] = None):
         d = LatticeDesc()
         for k in range(3):
             d.dims[k] = int(dims[k])
@@ -318,7 +334,8 @@ class Lattice:
         d.precision = VD_FP64 if precision == "fp64" else VD_FP32_FP64RED
         d.flags = ((VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
                    | (VD_FLAG_PROFILE if profile else 0)
-                   | (VD_FLAG_PERSIST if persistent else 0))
+                   | (VD_FLAG_PERSIST if persistent else 0)
+                   | (VD_FLAG_ACTIVE_SET if active_set else 0))
         for k in range(VD_MAX_LEVELS):
             d.tile[k] = int(tiles[k]) if tiles is not None and k < len(tiles) else 0
         self.desc = d
@@ -476,6 +493,65 @@ class Lattice:
         del keep
 
     # ---- test entry points ------------------------------------------
+    def get_active(self, level: int = -1):
+        """(mask (N,) bool, count, growth layers of the last build) of the
+        optimised set M of a level (every point without active_set)."""
+        lvl = self.num_levels - 1 if level < 0 else level
+        n = self.n_nodes(lvl)
+        mask = np.empty(n, np.uint8)
+        cnt = C.c_int64()
+        layers = C.c_int32()
+        _check(_lib.vd_get_active(self._h, lvl, mask.ctypes.data, C.byref(cnt), C.byref(layers)),
+               "vd_get_active")
+        return mask.astype(bool), int(cnt.value), int(layers.value)
+
+    # ---- fusion and mesh extraction (vd_fusion.h) ------------------------
+    def fuse_depth(self, tau: float, w_max: float = 64.0, k_min: int = 3,
+                   all_points: bool = False, count: bool = True):
+        """Fuse the handle's depth frame into its TSDF; returns the number of
+        grid points updated (None with count=False: asynchronous)."""
+        o = FuseOpts()
+        o.tau, o.w_max, o.k_min, o.all_points = float(tau), float(w_max), int(k_min), int(all_points)
+        if not count:
+            _check(_lib.vd_fuse_depth(self._h, C.byref(o), None), "vd_fuse_depth")
+            return None
+        n = C.c_int64()
+        _check(_lib.vd_fuse_depth(self._h, C.byref(o), C.byref(n)), "vd_fuse_depth")
+        return int(n.value)
+
+    def get_tsdf(self):
+        n = self.n_nodes()
+        D = np.empty(n, np.float32)
+        W = np.empty(n, np.float32)
+        F = np.empty(n, np.int32)
+        _check(_lib.vd_get_tsdf(self._h, D.ctypes.data, W.ctypes.data, F.ctypes.data,
+                                VD_MEM_HOST), "vd_get_tsdf")
+        return D, W, F
+
+    def set_tsdf(self, D, W) -> None:
+        D = np.ascontiguousarray(D, np.float32)
+        W = np.ascontiguousarray(W, np.float32)
+        _check(_lib.vd_set_tsdf(self._h, D.ctypes.data, W.ctypes.data, VD_MEM_HOST),
+               "vd_set_tsdf")
+
+    def extract_mesh(self):
+        """Marching cubes: (canonical vertices (T,3,3), deformed vertices
+        (T,3,3), cells (T,), edge numbers (T,3))."""
+        n = C.c_int64()
+        rc = _lib.vd_extract_mesh(self._h, 0, None, None, None, None, C.byref(n), VD_MEM_HOST)
+        if rc not in (VD_OK, VD_ERANGE):
+            _check(rc, "vd_extract_mesh")
+        T = int(n.value)
+        canon = np.empty((T, 3, 3), np.float32)
+        deformed = np.empty((T, 3, 3), np.float32)
+        cells = np.empty(T, np.int32)
+        edges = np.empty((T, 3), np.int32)
+        if T:
+            _check(_lib.vd_extract_mesh(self._h, T, canon.ctypes.data, deformed.ctypes.data,
+                                        cells.ctypes.data, edges.ctypes.data, C.byref(n),
+                                        VD_MEM_HOST), "vd_extract_mesh")
+        return canon, deformed, cells, edges
+
     # ---- tracking (vd_track.h) --------------------------------------------
     def set_depth_frame(self, frame, sparse_canon=None, sparse_target=None,
                         eps=(0.05, 0.3, 0.95)) -> None:

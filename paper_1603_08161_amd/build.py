@@ -18,10 +18,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvd.so")
 SOURCES = ["kernels.hip", "solve.hip", "sort.hip", "net.hip", "track.hip", "noalloc.hip",
-           "api.hip"]
-# track.hip takes its association decisions in float64 in the written operation
-# order, so no product may be fused into a following sum there.
-EXTRA_FLAGS = {"track.hip": ["-ffp-contract=off"]}
+           "fusion.hip", "api.hip"]
+# track.hip and fusion.hip take their decisions and stored values in float64
+# in the written operation order, so no product may be fused into a following
+# sum there.
+EXTRA_FLAGS = {"track.hip": ["-ffp-contract=off"], "fusion.hip": ["-ffp-contract=off"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

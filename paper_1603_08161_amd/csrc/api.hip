@@ -12,8 +12,10 @@
 #include "../../include/vd.h"
 #include "../../include/vd_net.h"
 #include "../../include/vd_track.h"
+#include "../../include/vd_fusion.h"
 #include "net_kernels.h"
 #include "track_kernels.h"
+#include "fusion_kernels.h"
 #include "vd_device.h"
 #include "vd_kernels.h"
 
@@ -129,6 +131,7 @@ struct LevelData {
     *ap2 = nullptr, *dinv = nullptr, *bnode = nullptr, *base = nullptr, *rot = nullptr;
   int* cell_map = nullptr;
   int* node_slot = nullptr;  // node -> row of A27r (-1: no data term)
+  unsigned char* act = nullptr;  // optimised set M (VD_FLAG_ACTIVE_SET), else null
   T* A27r = nullptr;         // [N][kA27Row] 27-point data blocks of A, per node slot
   Scalars* sc = nullptr;
   double* scg[2] = {nullptr, nullptr};  // CG block partials [4][max_tiles], alternating
@@ -153,6 +156,7 @@ struct LevelData {
     v.dinv = dinv; v.bnode = bnode; v.base = base; v.rot = rot;
     v.scg0 = scg[0]; v.scg1 = scg[1]; v.pe = pe;
     v.cell_map = cell_map; v.K = K; v.node_slot = node_slot; v.A27r = A27r;
+    v.act = act;
     v.row_cell = row_cell; v.row_f = row_f; v.row_sn = row_sn; v.row_rho = row_rho;
     v.sc = sc;
     return v;
@@ -227,6 +231,12 @@ class ISolver {
   virtual int track_frame(const vd_track_opts* o, vd_track_report* r) = 0;
   virtual int debug_associate(const float* disp, const float* rot, float* target, float* normal,
                               float* weight, int* pixel, int mem) = 0;
+  virtual int get_active(int level, unsigned char* mask, int64_t* count, int* layers) = 0;
+  virtual int fuse_depth(const vd_fuse_opts* o, int64_t* n_updated) = 0;
+  virtual int get_tsdf(float* D, float* W, int* frames, int mem) = 0;
+  virtual int set_tsdf(const float* D, const float* W, int mem) = 0;
+  virtual int extract_mesh(int64_t capacity, float* canon, float* deformed, int* cells,
+                           int* edges, int64_t* n_tri, int mem) = 0;
 };
 
 template <typename T>
@@ -286,6 +296,10 @@ class Solver final : public ISolver {
       VD_TRY(hipMemsetAsync(v.sc, 0, sizeof(Scalars), stream_));
       VD_CHECK(pool_.alloc(&v.r2, 3 * N));
       VD_CHECK(pool_.alloc(&v.ap2, 3 * N));
+      if (desc_.flags & VD_FLAG_ACTIVE_SET) {
+        VD_CHECK(pool_.alloc(&v.act, N));
+        VD_TRY(hipMemsetAsync(v.act, 1, N, stream_));
+      }
       VD_CHECK(pool_.alloc(&v.scg[0], 4 * (size_t)v.max_tiles));
       VD_CHECK(pool_.alloc(&v.scg[1], 4 * (size_t)v.max_tiles));
       VD_CHECK(ensure_partials(v, 0));
@@ -293,6 +307,18 @@ class Solver final : public ISolver {
     if ((desc_.flags & VD_FLAG_PROFILE) && (desc_.flags & VD_FLAG_GRAPH))
       VD_CHECK(pool_.alloc(&stamps_, 2 * kMaxStamped));  // written by captured CG launches
     VD_CHECK(pool_.alloc(&node_flags_, (size_t)finest().N));
+    // the canonical TSDF on the finest grid (Sec. 4): D = W = 0, never observed
+    VD_CHECK(pool_.alloc(&tsdf_d_, (size_t)finest().N));
+    VD_CHECK(pool_.alloc(&tsdf_w_, (size_t)finest().N));
+    VD_CHECK(pool_.alloc(&frames_, (size_t)finest().N));
+    VD_TRY(hipMemsetAsync(tsdf_d_, 0, sizeof(float) * finest().N, stream_));
+    VD_TRY(hipMemsetAsync(tsdf_w_, 0, sizeof(float) * finest().N, stream_));
+    VD_TRY(hipMemsetAsync(frames_, 0, sizeof(int) * finest().N, stream_));
+    if (desc_.flags & VD_FLAG_ACTIVE_SET) {
+      VD_CHECK(pool_.alloc(&prev_act_, (size_t)finest().N));
+      VD_CHECK(pool_.alloc(&known_, (size_t)finest().N));
+      VD_CHECK(pool_.alloc(&fresh_, (size_t)finest().N));
+    }
     VD_CHECK(pool_.alloc(&node_scan_, (size_t)finest().N));
     VD_CHECK(pool_.alloc(&d_flags_, 4));
     VD_TRY(hipHostMalloc((void**)&h_flags_, 4 * sizeof(int), hipHostMallocDefault));
@@ -368,6 +394,9 @@ class Solver final : public ISolver {
       }
       VD_TRY(launch_build_cells<T>(V, R, v.K, std::min(v.cap_cells, 8192), stream_));
       VD_TRY(launch_node_flags<T>(V, node_flags_, stream_));
+      // the optimised set M: the isosurface points (corners of the cells
+      // holding samples) and their one-ring
+      if (v.act) VD_TRY(launch_dilate<T>(V, node_flags_, v.act, stream_));
       VD_TRY(exclusive_scan(sort_temp_, sort_temp_bytes_, node_flags_, node_scan_, v.N, stream_));
       VD_TRY(launch_assemble_nodes<T>(V, R, node_flags_, node_scan_, v.node_slot, v.A27r,
                                       stream_));
@@ -377,6 +406,37 @@ class Solver final : public ISolver {
     n_dense_ = C;
     have_constraints_ = true;
     energy_fresh_ = false;
+    if (structure && finest().act) VD_CHECK(grow());
+    return VD_OK;
+  }
+
+  // Grid growth (Sec. 8): points of the finest level's new M that were not in
+  // the previous M are initialised by extrapolating the deformation field,
+  // layer by layer from the points already known (the previous M, then the
+  // earlier layers).  The first build has no previous M and extrapolates
+  // nothing.  Waits for the stream after every layer.
+  int grow() {
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    growth_layers_ = 0;
+    if (have_prev_act_) {
+      VD_CHECK(ensure_debug());
+      const LevelView<T> FV = F.view(desc_.w_arap);
+      VD_TRY(hipMemcpyAsync(known_, prev_act_, N, hipMemcpyDeviceToDevice, stream_));
+      for (;;) {
+        VD_TRY(launch_fill_int(d_flags_ + 1, 1, 0, stream_));
+        VD_TRY(launch_grow_layer<T>(FV, F.act, known_, dbg_t1_, dbg_t2_, fresh_, d_flags_ + 1,
+                                    stream_));
+        VD_TRY(hipMemcpyAsync(h_flags_ + 1, d_flags_ + 1, sizeof(int), hipMemcpyDeviceToHost,
+                              stream_));
+        VD_TRY(hipStreamSynchronize(stream_));
+        if (h_flags_[1] == 0) break;
+        VD_TRY(launch_grow_commit<T>(FV, dbg_t1_, dbg_t2_, fresh_, known_, stream_));
+        ++growth_layers_;
+      }
+    }
+    VD_TRY(hipMemcpyAsync(prev_act_, F.act, N, hipMemcpyDeviceToDevice, stream_));
+    have_prev_act_ = true;
     return VD_OK;
   }
 
@@ -405,6 +465,7 @@ class Solver final : public ISolver {
       VD_CHECK(enqueue_frame(reset, stream_));
     }
     energy_fresh_ = true;
+    VD_TRY(launch_count_frames<T>(finest().view(desc_.w_arap), frames_, stream_));
     if (rep) {
       std::memset(rep, 0, sizeof(*rep));
       VD_TRY(hipStreamSynchronize(stream_));
@@ -600,6 +661,7 @@ class Solver final : public ISolver {
     VD_TRY(launch_fill_float(st_weight_, (int64_t)C, 0.0f, stream_));
     if (S > 0) VD_TRY(launch_to_model_frame(pose_d_, st_stcam_, st_starget_, S, stream_));
     cam_ = cam;
+    have_depth_ = true;
     n_model_ = C;
     n_fsparse_ = S;
     VD_CHECK(build_levels(track_raw(), C, S, true));
@@ -655,6 +717,7 @@ class Solver final : public ISolver {
       }
     }
     energy_fresh_ = o->icp_iters > 0;
+    if (o->icp_iters > 0) VD_TRY(launch_count_frames<T>(FV, frames_, stream_));
     if (!rep) return VD_OK;
     std::memset(rep, 0, sizeof(*rep));
     if (!energy_fresh_) {
@@ -718,6 +781,147 @@ class Solver final : public ISolver {
     }
     VD_TRY(hipStreamSynchronize(stream_));
     return VD_OK;
+  }
+
+  int get_active(int level, unsigned char* mask, int64_t* count, int* layers) override {
+    if (level < 0 || level >= L_) return VD_EINVAL;
+    LevelData<T>& v = lv_[level];
+    std::vector<unsigned char> h(v.N, 1);
+    if (v.act) {
+      VD_TRY(hipMemcpyAsync(h.data(), v.act, v.N, hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+    }
+    if (mask) std::memcpy(mask, h.data(), v.N);
+    if (count) {
+      int64_t c = 0;
+      for (unsigned char b : h) c += b ? 1 : 0;
+      *count = c;
+    }
+    if (layers) *layers = growth_layers_;
+    return VD_OK;
+  }
+
+  // ---- fusion and mesh extraction (vd_fusion.h) ---------------------------
+  int fuse_depth(const vd_fuse_opts* o, int64_t* n_updated) override {
+    if (!o) return VD_EINVAL;
+    if (!(o->tau > 0.0) || !std::isfinite(o->tau) || !(o->w_max >= 1.0) ||
+        !std::isfinite(o->w_max) || o->k_min < 0)
+      return VD_EINVAL;
+    if (!have_depth_) return VD_ESTATE;
+    const LevelData<T>& F = finest();
+    FuseParams p;
+    p.W = cam_.W; p.H = cam_.H;
+    p.fx = cam_.fx; p.fy = cam_.fy; p.cx = cam_.cx; p.cy = cam_.cy;
+    p.ox = desc_.origin[0]; p.oy = desc_.origin[1]; p.oz = desc_.origin[2]; p.h = F.h;
+    p.tau = o->tau; p.w_max = o->w_max; p.k_min = o->k_min; p.all_points = o->all_points ? 1 : 0;
+    if (n_updated) VD_TRY(launch_fill_int(d_flags_ + 2, 1, 0, stream_));
+    VD_TRY(launch_fuse<T>(p, F.view(desc_.w_arap), depth_, pose_d_, frames_, tsdf_d_, tsdf_w_,
+                          d_flags_ + 2, stream_));
+    if (n_updated) {
+      VD_TRY(hipMemcpyAsync(h_flags_ + 2, d_flags_ + 2, sizeof(int), hipMemcpyDeviceToHost,
+                            stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+      *n_updated = h_flags_[2];
+    }
+    return VD_OK;
+  }
+
+  int get_tsdf(float* D, float* W, int* frames, int mem) override {
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    const size_t N = finest().N;
+    const hipMemcpyKind k = mem == VD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (D) VD_TRY(hipMemcpyAsync(D, tsdf_d_, 4 * N, k, stream_));
+    if (W) VD_TRY(hipMemcpyAsync(W, tsdf_w_, 4 * N, k, stream_));
+    if (frames) VD_TRY(hipMemcpyAsync(frames, frames_, 4 * N, k, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  int set_tsdf(const float* D, const float* W, int mem) override {
+    if (!D || !W || (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE)) return VD_EINVAL;
+    const size_t N = finest().N;
+    VD_CHECK(ensure_debug());
+    const hipMemcpyKind k = mem == VD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    VD_TRY(hipMemcpyAsync(dbg_f_, D, 4 * N, k, stream_));
+    VD_TRY(hipMemcpyAsync(dbg_f_ + N, W, 4 * N, k, stream_));
+    VD_TRY(hipMemsetAsync(d_flags_, 0, sizeof(int), stream_));
+    VD_TRY(launch_check_finite(dbg_f_, 2 * (int64_t)N, d_flags_, stream_));
+    VD_TRY(hipMemcpyAsync(h_flags_, d_flags_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    if (h_flags_[0]) return VD_EINVAL;
+    std::vector<float> w(N);
+    VD_TRY(hipMemcpy(w.data(), dbg_f_ + N, 4 * N, hipMemcpyDeviceToHost));
+    for (float x : w)
+      if (x < 0.0f) return VD_EINVAL;
+    VD_TRY(hipMemcpyAsync(tsdf_d_, dbg_f_, 4 * N, hipMemcpyDeviceToDevice, stream_));
+    VD_TRY(hipMemcpyAsync(tsdf_w_, dbg_f_ + N, 4 * N, hipMemcpyDeviceToDevice, stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    return VD_OK;
+  }
+
+  int extract_mesh(int64_t capacity, float* canon, float* deformed, int* cells, int* edges,
+                   int64_t* n_tri, int mem) override {
+    if (!n_tri || capacity < 0 || (capacity > 0 && !canon)) return VD_EINVAL;
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    if (mc_table_ready() != 0) return VD_EHIP;
+    const LevelData<T>& F = finest();
+    const int ncell = F.ncell;
+    if (!mc_counts_) {
+      VD_CHECK(pool_.alloc(&mc_counts_, (size_t)ncell));
+      VD_CHECK(pool_.alloc(&mc_offsets_, (size_t)ncell));
+      mc_scan_bytes_ = vd::scan_temp_bytes(ncell);
+      VD_CHECK(pool_.alloc((unsigned char**)&mc_scan_temp_, mc_scan_bytes_));
+    }
+    VD_TRY(launch_mc_count(tsdf_d_, tsdf_w_, F.nx, F.ny, F.nz, mc_counts_, stream_));
+    VD_TRY(exclusive_scan(mc_scan_temp_, mc_scan_bytes_, mc_counts_, mc_offsets_, ncell, stream_));
+    int last[2] = {0, 0};
+    VD_TRY(hipMemcpyAsync(&last[0], mc_offsets_ + ncell - 1, sizeof(int), hipMemcpyDeviceToHost,
+                          stream_));
+    VD_TRY(hipMemcpyAsync(&last[1], mc_counts_ + ncell - 1, sizeof(int), hipMemcpyDeviceToHost,
+                          stream_));
+    VD_TRY(hipStreamSynchronize(stream_));
+    const int64_t total = (int64_t)last[0] + last[1];
+    *n_tri = total;
+    if (total > capacity) return VD_ERANGE;
+    if (total == 0) return VD_OK;
+    float *dc = canon, *dd = deformed;
+    int *dcell = cells, *dedge = edges;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+      for (void* b : tmp) (void)hipFree(b);
+    };
+    if (mem == VD_MEM_HOST) {
+      // temporaries of a synchronous host-bound call
+      const size_t sz[4] = {36 * (size_t)total, deformed ? 36 * (size_t)total : 0,
+                            cells ? 4 * (size_t)total : 0, edges ? 12 * (size_t)total : 0};
+      void* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+      for (int k = 0; k < 4; ++k) {
+        if (!sz[k]) continue;
+        if (hipMalloc(&bufs[k], sz[k]) != hipSuccess) {
+          (void)hipGetLastError();
+          cleanup();
+          return VD_ENOMEM;
+        }
+        tmp.push_back(bufs[k]);
+      }
+      dc = (float*)bufs[0]; dd = (float*)bufs[1]; dcell = (int*)bufs[2]; dedge = (int*)bufs[3];
+    }
+    MeshParams mp;
+    mp.ox = desc_.origin[0]; mp.oy = desc_.origin[1]; mp.oz = desc_.origin[2]; mp.h = F.h;
+    hipError_t e = launch_mc_emit<T>(mp, F.view(desc_.w_arap), tsdf_d_, tsdf_w_, mc_counts_,
+                                     mc_offsets_, pose_d_, dc, dd, dcell, dedge, stream_);
+    if (e == hipSuccess && mem == VD_MEM_HOST) {
+      e = hipMemcpyAsync(canon, dc, 36 * (size_t)total, hipMemcpyDeviceToHost, stream_);
+      if (e == hipSuccess && deformed)
+        e = hipMemcpyAsync(deformed, dd, 36 * (size_t)total, hipMemcpyDeviceToHost, stream_);
+      if (e == hipSuccess && cells)
+        e = hipMemcpyAsync(cells, dcell, 4 * (size_t)total, hipMemcpyDeviceToHost, stream_);
+      if (e == hipSuccess && edges)
+        e = hipMemcpyAsync(edges, dedge, 12 * (size_t)total, hipMemcpyDeviceToHost, stream_);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    cleanup();
+    return e == hipSuccess ? VD_OK : VD_EHIP;
   }
 
   // ---- accessors used by the batched solve ---------------------------
@@ -1349,6 +1553,21 @@ class Solver final : public ISolver {
   int* kept_d_ = nullptr;         // kept pairs per association round
   float* dbg_assoc_ = nullptr;    // host-bound association outputs (test entry)
   size_t dbg_assoc_cap_ = 0;
+  // optimised set M (VD_FLAG_ACTIVE_SET)
+  unsigned char* prev_act_ = nullptr;  // the finest M of the previous build
+  unsigned char* known_ = nullptr;     // grid growth: points already initialised
+  unsigned char* fresh_ = nullptr;     // grid growth: the current layer
+  bool have_prev_act_ = false;
+  int growth_layers_ = 0;
+  // canonical TSDF (vd_fusion.h)
+  float* tsdf_d_ = nullptr;
+  float* tsdf_w_ = nullptr;
+  int* frames_ = nullptr;      // frames in a row each finest point has been in M
+  bool have_depth_ = false;
+  int* mc_counts_ = nullptr;   // marching cubes: triangles per cell
+  int* mc_offsets_ = nullptr;  // their exclusive prefix sum
+  void* mc_scan_temp_ = nullptr;
+  size_t mc_scan_bytes_ = 0;
 };
 
 // ===========================================================================
@@ -1451,6 +1670,7 @@ class Batch final : public IBatch {
     LevelView<T>* views = nullptr;
     int* starts[4] = {nullptr, nullptr, nullptr, nullptr};
     int blocks[4] = {0, 0, 0, 0};
+    int masked = 0;  // some lattice restricts its solve to its set M
     LevelView<T> first{};
   };
 
@@ -1469,6 +1689,8 @@ class Batch final : public IBatch {
       }
       Tables& t = tables_[l];
       t.first = views[0];
+      t.masked = 0;
+      for (const LevelView<T>& V : views) t.masked |= V.act != nullptr;
       VD_TRY(hipMemcpy(t.views, views.data(), sizeof(LevelView<T>) * n_, hipMemcpyHostToDevice));
       for (int k = 0; k < 4; ++k) {
         VD_TRY(hipMemcpy(t.starts[k], st[k].data(), sizeof(int) * (n_ + 1),
@@ -1488,6 +1710,7 @@ class Batch final : public IBatch {
     d.starts = t.starts[kind];
     d.n = n_;
     d.blocks = t.blocks[kind];
+    d.masked = t.masked;
     return d;
   }
 
@@ -2028,6 +2251,33 @@ int vd_set_pose(vd_lattice* l, const double pose[12]) {
 int vd_track_frame(vd_lattice* l, const vd_track_opts* o, vd_track_report* r) {
   if (!l) return VD_EINVAL;
   return l->impl->track_frame(o, r);
+}
+
+int vd_fuse_depth(vd_lattice* l, const vd_fuse_opts* o, int64_t* n_updated) {
+  if (!l) return VD_EINVAL;
+  return l->impl->fuse_depth(o, n_updated);
+}
+
+int vd_get_tsdf(vd_lattice* l, float* D, float* W, int32_t* frames, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_tsdf(D, W, frames, mem);
+}
+
+int vd_set_tsdf(vd_lattice* l, const float* D, const float* W, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->set_tsdf(D, W, mem);
+}
+
+int vd_extract_mesh(vd_lattice* l, int64_t capacity, float* canon, float* deformed,
+                    int32_t* cells, int32_t* edges, int64_t* n_triangles, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->extract_mesh(capacity, canon, deformed, cells, edges, n_triangles, mem);
+}
+
+int vd_get_active(vd_lattice* l, int32_t level, uint8_t* mask, int64_t* count,
+                  int32_t* growth_layers) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_active(level, mask, count, growth_layers);
 }
 
 int vd_debug_associate(vd_lattice* l, const float* disp, const float* rot, float* target,

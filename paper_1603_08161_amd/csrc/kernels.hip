@@ -404,12 +404,116 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
     dg[2] = acc[13][5];
   }
   const size_t N = L.N;
-  const T arap = T(2) * L.wr * T(nb);
+  T arap = T(2) * L.wr * T(nb);
+  bool in_set = true;
+  if (L.act) {
+    // restricted to M: only the edges inside M count, so the ARAP diagonal
+    // is 2 w_r |N_i and M|; points outside M are not unknowns (D^-1 = 0)
+    in_set = L.act[i] != 0;
+    int w = 0;
+    const size_t st[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+    const int pos[3] = {x, y, z};
+    const int lim[3] = {L.nx, L.ny, L.nz};
+    for (int ax = 0; ax < 3; ++ax) {
+      if (pos[ax] > 0) w += L.act[i - st[ax]];
+      if (pos[ax] < lim[ax] - 1) w += L.act[i + st[ax]];
+    }
+    arap = T(2) * L.wr * T(w);
+  }
   for (int k = 0; k < 3; ++k) {
     const T dk = arap + dg[k];
-    L.dinv[k * N + i] = dk > T(0) ? T(1) / dk : T(0);
+    L.dinv[k * N + i] = (in_set && dk > T(0)) ? T(1) / dk : T(0);
     L.bnode[k * N + i] = b[k];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dilate(LevelView<T> L, const int* flags,
+                                                   unsigned char* act) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const size_t st[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+  const int pos[3] = {x, y, z};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+  int f = flags[i];
+  for (int ax = 0; ax < 3; ++ax) {
+    if (pos[ax] > 0) f |= flags[i - st[ax]];
+    if (pos[ax] < lim[ax] - 1) f |= flags[i + st[ax]];
+  }
+  act[i] = f ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_dilate(const LevelView<T>& L, const int* flags, unsigned char* act,
+                         hipStream_t s) {
+  k_dilate<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, flags, act);
+  return hipGetLastError();
+}
+
+// Grid growth, one layer (Sec. 8: points that join M for the first time are
+// initialised by extrapolating the deformation field).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grow_layer(LevelView<T> L, const unsigned char* act,
+                                                       const unsigned char* known, T* tmp_d,
+                                                       T* tmp_r, unsigned char* fresh,
+                                                       int* count) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  fresh[i] = 0;
+  if (!act[i] || known[i]) return;
+  const size_t N = L.N;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const size_t st[3] = {1, (size_t)L.nx, (size_t)L.nx * L.ny};
+  const int pos[3] = {x, y, z};
+  const int lim[3] = {L.nx, L.ny, L.nz};
+  double acc[3] = {0.0, 0.0, 0.0};
+  int cnt = 0;
+  long first = -1;
+  for (int ax = 0; ax < 3; ++ax) {
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const int pj = pos[ax] + sgn;
+      if (pj < 0 || pj >= lim[ax]) continue;
+      const size_t j = sgn > 0 ? i + st[ax] : i - st[ax];
+      if (!known[j]) continue;
+      for (int k = 0; k < 3; ++k) acc[k] += (double)L.d[k * N + j];
+      ++cnt;
+      if (first < 0) first = (long)j;
+    }
+  }
+  if (!cnt) return;
+  for (int k = 0; k < 3; ++k) tmp_d[k * N + i] = (T)(acc[k] / cnt);
+  for (int k = 0; k < 9; ++k) tmp_r[k * N + i] = L.rot[k * N + (size_t)first];
+  fresh[i] = 1;
+  atomicAdd(count, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grow_commit(LevelView<T> L, const T* tmp_d,
+                                                        const T* tmp_r, unsigned char* fresh,
+                                                        unsigned char* known) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N || !fresh[i]) return;
+  const size_t N = L.N;
+  for (int k = 0; k < 3; ++k) L.d[k * N + i] = tmp_d[k * N + i];
+  for (int k = 0; k < 9; ++k) L.rot[k * N + i] = tmp_r[k * N + i];
+  known[i] = 1;
+  fresh[i] = 0;
+}
+
+template <typename T>
+hipError_t launch_grow_layer(const LevelView<T>& L, const unsigned char* act,
+                             const unsigned char* known, T* tmp_d, T* tmp_r,
+                             unsigned char* fresh, int* count, hipStream_t s) {
+  k_grow_layer<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, act, known, tmp_d, tmp_r, fresh, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grow_commit(const LevelView<T>& L, const T* tmp_d, const T* tmp_r,
+                              unsigned char* fresh, unsigned char* known, hipStream_t s) {
+  k_grow_commit<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, tmp_d, tmp_r, fresh, known);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -583,6 +687,13 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
                                                const int*, const int*, int*, T*,             \
                                                hipStream_t);                                    \
   template hipError_t launch_node_flags<T>(const LevelView<T>&, int*, hipStream_t);             \
+  template hipError_t launch_dilate<T>(const LevelView<T>&, const int*, unsigned char*,         \
+                                       hipStream_t);                                             \
+  template hipError_t launch_grow_layer<T>(const LevelView<T>&, const unsigned char*,           \
+                                           const unsigned char*, T*, T*, unsigned char*, int*,  \
+                                           hipStream_t);                                         \
+  template hipError_t launch_grow_commit<T>(const LevelView<T>&, const T*, const T*,            \
+                                            unsigned char*, unsigned char*, hipStream_t);       \
   template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \
                                          const float*, const float*, int, int*, hipStream_t);   \
   template hipError_t launch_convert<T>(const float*, T*, int, hipStream_t);                    \

@@ -144,15 +144,37 @@ struct TilePos {
 
 // ARAP part of A p at own node c (tile-local) / i (global) from the tile's p
 // in LDS: 2 w_r times the 6-neighbour Laplacian.  The data part is added by
-// the caller (eval_data_nodes).
+// the caller (eval_data_nodes).  With the optimised set M (sm: the tile's
+// membership in LDS) only the edges inside M count: node c couples to the
+// neighbours q in M.
 template <typename T, typename TL>
 __device__ __forceinline__ void arap_at(const LevelView<T>& L, const T (*sp)[TL::HALO], int c,
-                                        int gx, int gy, int gz, T& o0, T& o1, T& o2) {
+                                        int gx, int gy, int gz, T& o0, T& o1, T& o2,
+                                        const unsigned char* sm = nullptr) {
   const T p0 = sp[0][c], p1 = sp[1][c], p2 = sp[2][c];
   T l0 = T(0), l1 = T(0), l2 = T(0);
   const int off[3] = {1, TL::HX, TL::HX * TL::HY};
   const int pos[3] = {gx, gy, gz};
   const int lim[3] = {L.nx, L.ny, L.nz};
+  if (sm) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        if (sgn < 0 ? pos[ax] == 0 : pos[ax] == lim[ax] - 1) continue;
+        const int q = sgn < 0 ? c - off[ax] : c + off[ax];
+        if (!sm[q]) continue;
+        l0 += p0 - sp[0][q];
+        l1 += p1 - sp[1][q];
+        l2 += p2 - sp[2][q];
+      }
+    }
+    const T w2 = T(2) * L.wr;
+    o0 = w2 * l0;
+    o1 = w2 * l1;
+    o2 = w2 * l2;
+    return;
+  }
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     if (pos[ax] > 0) {
@@ -276,10 +298,11 @@ __device__ __forceinline__ void eval_data_nodes(const LevelView<T>& L,
 // kModeRhs : p = d; g = A d - b + w_r sum_j (2I - R_i - R_j) e_ij is the
 //            gradient J^T r; r = -g is stored (the CG residual r_0).
 // kModeApply / kModeGrad : A p or g written to `out` (test entry points).
-template <typename T, typename TL, int MODE>
+template <typename T, typename TL, int MODE, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
                                                     T* __restrict__ out) {
   __shared__ T sp[3][TL::HALO];
+  __shared__ unsigned char sm[TL::HALO];
   __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   const LevelView<T>& L = w.L;
@@ -288,6 +311,21 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
   const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
   // the CG solve that follows a gradient pass counts its grid barrier from 0
   if (MODE == kModeRhs && w.local == 0 && threadIdx.x == 0) L.sc->bar = 0u;
+  // MASK: the optimised set M (a lattice of the launch may still have none)
+  const unsigned char* __restrict__ act = MASK ? L.act : nullptr;
+  if (MODE == kModeRhs && act) {
+    // a tile without points of M has no unknowns (its r is never read)
+    int any = 0;
+#pragma unroll
+    for (int kk = 0; kk < TL::NPT; ++kk) {
+      const int c = TilePos<TL>::own(kk);
+      const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+      const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+      if (in_box(gx, gy, gz, L.nx, L.ny, L.nz))
+        any |= act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)];
+    }
+    if (!__syncthreads_or(any)) return;
+  }
   // own nodes' data-block slots (loaded with the tile)
   int own_slot[TL::NPT];
 #pragma unroll
@@ -303,15 +341,22 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     T v0 = T(0), v1 = T(0), v2 = T(0);
+    unsigned char m = 0;
     if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
-      v0 = src[i];
-      v1 = src[N + i];
-      v2 = src[2 * N + i];
+      m = act ? act[i] : 1;
+      // A p acts on the unknowns of M only; the gradient reads the stored
+      // displacement of every point
+      if (MODE != kModeApply || m) {
+        v0 = src[i];
+        v1 = src[N + i];
+        v2 = src[2 * N + i];
+      }
     }
     sp[0][k] = v0;
     sp[1][k] = v1;
     sp[2][k] = v2;
+    if (MASK) sm[k] = m;
   }
   int rank[TL::NPT];
   list_data_nodes<T, TL>(own_slot, ds, rank);
@@ -325,8 +370,16 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    if (act && !act[i]) {
+      // not an unknown: zero gradient / product
+      T* __restrict__ dst = (MODE == kModeRhs) ? L.r : out;
+      dst[i] = T(0);
+      dst[N + i] = T(0);
+      dst[2 * N + i] = T(0);
+      continue;
+    }
     T o0, o1, o2;
-    arap_at<T, TL>(L, sp, c, gx, gy, gz, o0, o1, o2);
+    arap_at<T, TL>(L, sp, c, gx, gy, gz, o0, o1, o2, act ? sm : nullptr);
     if (rank[kk] >= 0) {
       const int e = (threadIdx.x / kWave) * DataShare<T, TL>::SEG + rank[kk];
       o0 += ds.d[0][e];
@@ -357,6 +410,7 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
         const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
         const T cj0 = rot[rot_at(0, ax, N, j)], cj1 = rot[rot_at(1, ax, N, j)],
                 cj2 = rot[rot_at(2, ax, N, j)];
+        if (act && !act[j]) continue;  // only the edges inside M
         const T s = -T(sgn) * L.h;
         T u0 = -ci0 - cj0, u1 = -ci1 - cj1, u2 = -ci2 - cj2;
         if (ax == 0) u0 += T(2);
@@ -378,13 +432,23 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
   }
 }
 
+template <typename T, typename TL, bool MASK>
+void launch_stencil_m(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s) {
+  switch (mode) {
+    case kModeRhs:
+      k_stencil<T, TL, kModeRhs, MASK><<<D.blocks, TL::NT, 0, s>>>(D, pin, out);
+      break;
+    case kModeApply:
+      k_stencil<T, TL, kModeApply, MASK><<<D.blocks, TL::NT, 0, s>>>(D, pin, out);
+      break;
+    default: k_stencil<T, TL, kModeGrad, MASK><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
+  }
+}
+
 template <typename T, typename TL>
 void launch_stencil_t(int mode, const Dispatch<T>& D, const T* pin, T* out, hipStream_t s) {
-  switch (mode) {
-    case kModeRhs: k_stencil<T, TL, kModeRhs><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
-    case kModeApply: k_stencil<T, TL, kModeApply><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
-    default: k_stencil<T, TL, kModeGrad><<<D.blocks, TL::NT, 0, s>>>(D, pin, out); break;
-  }
+  if (D.masked) launch_stencil_m<T, TL, true>(mode, D, pin, out, s);
+  else launch_stencil_m<T, TL, false>(mode, D, pin, out, s);
 }
 
 // The tile kind is common to all lattices of a launch.
@@ -460,9 +524,10 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, Step<T>& alph
 // together with the halo (shorter dependent chain, more registers) instead of
 // at their use.  The data-block slots are loaded early in both forms: the
 // workgroup's list of data nodes needs them before the tile is staged.
-template <typename T, typename TL, bool FIRST, bool PF = true>
+template <typename T, typename TL, bool FIRST, bool PF = true, bool MASK = false>
 __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
-                                        T (&sr)[3][TL::HALO], DataShare<T, TL>& ds) {
+                                        T (&sr)[3][TL::HALO], unsigned char (&sm)[TL::HALO],
+                                        DataShare<T, TL>& ds) {
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
@@ -476,10 +541,36 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   const double* s_in = odd ? L.scg0 : L.scg1;
   double* s_out = odd ? L.scg1 : L.scg0;
   const T* __restrict__ dinv = L.dinv;
+  // MASK: the optimised set M (a lattice of the launch may still have none)
+  const unsigned char* __restrict__ act = MASK ? L.act : nullptr;
+  if (act) {
+    // restricted to M: a tile without points of M has no unknowns; its
+    // partials are zero.  Points outside M are read as 0 below and their
+    // vectors never written.
+    int any = 0;
+#pragma unroll
+    for (int kk = 0; kk < TL::NPT; ++kk) {
+      const int c = TilePos<TL>::own(kk);
+      const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
+      const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
+      if (in_box(gx, gy, gz, L.nx, L.ny, L.nz))
+        any |= act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)];
+    }
+    if (!__syncthreads_or(any)) {
+      if (!FIRST && w.local == 0) {
+        Step<T> a0, b0;
+        cg_scalars<T, TL::NT>(s_in, L.ntiles, a0, b0, L.sc, true);
+      }
+      double zero[4] = {0.0, 0.0, 0.0, 0.0};
+      write_partials<4, TL::NT>(zero, s_out, w.count, w.local);
+      return;
+    }
+  }
   // 1. halo inputs into registers
   T hr[TL::HPT][3], hq[TL::HPT][3], hp[TL::HPT][3], ha[TL::HPT][3];
   size_t hi[TL::HPT];
   bool hin[TL::HPT];
+  unsigned char hm[TL::HPT];
 #pragma unroll
   for (int h = 0; h < TL::HPT; ++h) {
     const int k = threadIdx.x + h * TL::NT;
@@ -487,6 +578,8 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     hin[h] = k < TL::HALO && in_box(gx, gy, gz, L.nx, L.ny, L.nz);
     hi[h] = hin[h] ? gx + (size_t)L.nx * (gy + (size_t)L.ny * gz) : 0;
+    hm[h] = hin[h] ? (act ? act[hi[h]] : 1) : 0;
+    hin[h] = hin[h] && hm[h];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       hr[h][a] = T(0);
@@ -525,7 +618,8 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       own_d[kk][a] = T(0);
       own_pp[kk][a] = T(0);
     }
-    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz)) {
+    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz) &&
+        (!act || act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)])) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
       if (PF) {
@@ -562,6 +656,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       sp[a][k] = p;
       sr[a][k] = r;
     }
+    if (MASK) sm[k] = hm[h];
     const int lx = k % TL::HX, ly = (k / TL::HX) % TL::HY, lz = k / (TL::HX * TL::HY);
     if (hin[h] && lx >= 1 && lx <= TL::TX && ly >= 1 && ly <= TL::TY && lz >= 1 &&
         lz <= TL::TZ) {
@@ -586,10 +681,10 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     const int c = TilePos<TL>::own(kk);
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz) || (act && !sm[c])) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
-    arap_at<T, TL>(L, sp, c, gx, gy, gz, o[0], o[1], o[2]);
+    arap_at<T, TL>(L, sp, c, gx, gy, gz, o[0], o[1], o[2], act ? sm : nullptr);
     const int e = (threadIdx.x / kWave) * DataShare<T, TL>::SEG + rank[kk];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -615,29 +710,31 @@ __device__ __forceinline__ void entry_stamp(unsigned long long* stamp) {
     *stamp = (unsigned long long)wall_clock64();
 }
 
-template <typename T, typename TL, bool FIRST>
+template <typename T, typename TL, bool FIRST, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m, unsigned long long* stamp) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ unsigned char sm[TL::HALO];
   __shared__ DataShare<T, TL> ds;
   entry_stamp(stamp);
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST>(w, m, sp, sr, ds);
+  cg_body<T, TL, FIRST, true, MASK>(w, m, sp, sr, sm, ds);
 }
 
 // The same iteration with the own-node values loaded at their use: fewer
 // registers, so more resident waves.  For grids larger than one round of
 // workgroups (batched lattices) occupancy hides more latency than the
 // register-held prefetches of k_cg.
-template <typename T, typename TL, bool FIRST>
+template <typename T, typename TL, bool FIRST, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m,
                                                    unsigned long long* stamp) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ unsigned char sm[TL::HALO];
   __shared__ DataShare<T, TL> ds;
   entry_stamp(stamp);
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST, false>(w, m, sp, sr, ds);
+  cg_body<T, TL, FIRST, false, MASK>(w, m, sp, sr, sm, ds);
 }
 
 // Workgroups that fit in one round on 256 CUs at the register use of k_cg.
@@ -686,24 +783,26 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
+    if (L.act && !L.act[i]) continue;
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a * N + i] = alpha.axpy(d[a * N + i], p[a * N + i]);
   }
 }
 
 // All iterations of one CG solve (single lattice, every tile resident).
-template <typename T, typename TL>
+template <typename T, typename TL, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
+  __shared__ unsigned char sm[TL::HALO];
   __shared__ DataShare<T, TL> ds;
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
   Scalars* sc = w.L.sc;
   for (int m = 0; m < iters; ++m) {
     if (m == 0)
-      cg_body<T, TL, true>(w, m, sp, sr, ds);
+      cg_body<T, TL, true, true, MASK>(w, m, sp, sr, sm, ds);
     else
-      cg_body<T, TL, false>(w, m, sp, sr, ds);
+      cg_body<T, TL, false, true, MASK>(w, m, sp, sr, sm, ds);
     grid_barrier(&sc->bar, (unsigned)(m + 1) * gridDim.x, &sc->bar_timeouts);
   }
   cg_final_tile<T, TL>(w, iters - 1);
@@ -720,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
   Step<T> alpha, beta;
   cg_scalars<T>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
   const int i = w.local * kBlock + threadIdx.x;
-  if (i >= L.N) return;
+  if (i >= L.N || (L.act && !L.act[i])) return;
   const size_t N = L.N;
   const T* __restrict__ p = odd ? L.pb : L.pa;
   T* __restrict__ d = L.d;
@@ -731,11 +830,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
 template <typename T, typename TL>
 void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s, unsigned long long* stamp) {
   if ((long)D.blocks * TL::NT > (long)kOneRoundBlocks * kBlock) {
-    if (m == 0) k_cg_occ<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    else k_cg_occ<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    if (D.masked) {
+      if (m == 0) k_cg_occ<T, TL, true, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+      else k_cg_occ<T, TL, false, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    } else {
+      if (m == 0) k_cg_occ<T, TL, true, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+      else k_cg_occ<T, TL, false, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    }
   } else {
-    if (m == 0) k_cg<T, TL, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    else k_cg<T, TL, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    if (D.masked) {
+      if (m == 0) k_cg<T, TL, true, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+      else k_cg<T, TL, false, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    } else {
+      if (m == 0) k_cg<T, TL, true, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+      else k_cg<T, TL, false, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    }
   }
 }
 
@@ -762,20 +871,26 @@ hipError_t launch_cg_final(int last, const Dispatch<T>& D, hipStream_t s,
   return hipGetLastError();
 }
 
+template <typename T, bool MASK>
+void launch_cg_loop_t(int iters, const Dispatch<T>& D, hipStream_t s) {
+  switch (D.one.tile) {
+    case 1: k_cg_loop<T, TileM, MASK><<<D.blocks, TileM::NT, 0, s>>>(D, iters); break;
+    case 2: k_cg_loop<T, TileW, MASK><<<D.blocks, TileW::NT, 0, s>>>(D, iters); break;
+    case 3: k_cg_loop<T, TileX, MASK><<<D.blocks, TileX::NT, 0, s>>>(D, iters); break;
+    case 4: k_cg_loop<T, TileZ, MASK><<<D.blocks, TileZ::NT, 0, s>>>(D, iters); break;
+    case 5: k_cg_loop<T, TileY, MASK><<<D.blocks, TileY::NT, 0, s>>>(D, iters); break;
+    case 6: k_cg_loop<T, TileH, MASK><<<D.blocks, TileH::NT, 0, s>>>(D, iters); break;
+    default: k_cg_loop<T, TileS, MASK><<<D.blocks, TileS::NT, 0, s>>>(D, iters); break;
+  }
+}
+
 template <typename T>
 hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s) {
   if (D.blocks <= 0 || iters <= 0) return hipSuccess;
   if (D.n != 1 || D.blocks > kPersistMaxTiles || D.blocks != D.one.ntiles)
     return hipErrorInvalidValue;
-  switch (D.one.tile) {
-    case 1: k_cg_loop<T, TileM><<<D.blocks, TileM::NT, 0, s>>>(D, iters); break;
-    case 2: k_cg_loop<T, TileW><<<D.blocks, TileW::NT, 0, s>>>(D, iters); break;
-    case 3: k_cg_loop<T, TileX><<<D.blocks, TileX::NT, 0, s>>>(D, iters); break;
-    case 4: k_cg_loop<T, TileZ><<<D.blocks, TileZ::NT, 0, s>>>(D, iters); break;
-    case 5: k_cg_loop<T, TileY><<<D.blocks, TileY::NT, 0, s>>>(D, iters); break;
-    case 6: k_cg_loop<T, TileH><<<D.blocks, TileH::NT, 0, s>>>(D, iters); break;
-    default: k_cg_loop<T, TileS><<<D.blocks, TileS::NT, 0, s>>>(D, iters); break;
-  }
+  if (D.masked) launch_cg_loop_t<T, true>(iters, D, s);
+  else launch_cg_loop_t<T, false>(iters, D, s);
   return hipGetLastError();
 }
 
@@ -817,7 +932,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dispatch<T> D) {
     }
   } else {
     const int i = (w.local - L.rblocks) * kBlock + threadIdx.x;
-    if (i < L.N) {
+    // E_reg sums the edges inside M (all of them when the whole lattice is
+    // optimised)
+    if (i < L.N && (!L.act || L.act[i])) {
       const T* __restrict__ rot = L.rot;
       const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
       const int pos[3] = {x, y, z};
@@ -837,6 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dispatch<T> D) {
           const int pj = pos[ax] + sgn;
           if (pj < 0 || pj >= lim[ax]) continue;
           const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+          if (L.act && !L.act[j]) continue;
           const T s = -T(sgn) * L.h;
           const T e0 = d[i] - d[j] + s * c0;
           const T e1 = d[N + i] - d[N + j] + s * c1;
@@ -907,7 +1025,7 @@ __global__ __launch_bounds__(kBlock) void k_polar(Dispatch<T> D) {
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
   const int i = w.local * kBlock + threadIdx.x;
-  if (i >= L.N) return;
+  if (i >= L.N || (L.act && !L.act[i])) return;  // points outside M keep R
   const size_t N = L.N;
   const T* __restrict__ d = L.d;
   T* rot = L.rot;
@@ -927,6 +1045,7 @@ __global__ __launch_bounds__(kBlock) void k_polar(Dispatch<T> D) {
       const int pj = pos[ax] + sgn;
       if (pj < 0 || pj >= lim[ax]) continue;
       const size_t j = sgn > 0 ? i + stride[ax] : i - stride[ax];
+      if (L.act && !L.act[j]) continue;  // the terms of eq. (4) inside M
       // (d_i - d_j + e_ij) e_ij^T with e_ij = -s h axis: column ax gets
       // -s h (d_i - d_j) + h^2 axis
       const T s = -T(sgn) * L.h;
@@ -995,6 +1114,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Dispatch<T> D, Dispatch<T> C
   const LevelView<T>& Fl = w.L;
   const int i = w.local * kBlock + threadIdx.x;
   if (i >= Fl.N) return;
+  if (add && Fl.act && !Fl.act[i]) return;  // the increment reaches M only
   const LevelView<T> Cv = view_of(C, w.b);
   const int x = i % Fl.nx, y = (i / Fl.nx) % Fl.ny, z = i / (Fl.nx * Fl.ny);
   const int p[3] = {x, y, z};

@@ -61,6 +61,9 @@ struct LevelView {
   T* bnode;   // J^T (weighted targets) of the data rows, per node
   T* base;    // finest state injected to this level (for the increment)
   T* rot;     // rotations
+  // optimised set M (isosurface points plus their one-ring): 1 per node of
+  // M; null when every node is optimised
+  const unsigned char* act;
   double* scg0;  // CG block partials [4][ntiles], even / odd iterates
   double* scg1;
   double* pe;    // energy block partials [3][rblocks + node blocks]
@@ -87,6 +90,7 @@ struct Dispatch {
   const int* starts;          // device [n + 1] first workgroup of each lattice
   int n;
   int blocks;                 // total workgroups
+  int masked;                 // some lattice restricts the solve to its set M
 };
 
 // Constraint rows of one level (dense rows then 3 rows per sparse pair).
@@ -135,6 +139,26 @@ hipError_t launch_build_cells(const LevelView<T>& L, const RowView<T>& R, T* K, 
 
 template <typename T>
 hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s);
+
+// act[i] = flags[i] or a 6-neighbour's flag (the one-ring of the flagged
+// isosurface points).
+template <typename T>
+hipError_t launch_dilate(const LevelView<T>& L, const int* flags, unsigned char* act,
+                         hipStream_t s);
+
+// One layer of grid growth on a level: every node of act that is not
+// `known` and has a known 6-neighbour takes the mean of their displacements
+// and the rotation of the first of them in the order -x, +x, -y, +y, -z, +z
+// (written to tmp_d [3][N], tmp_r [9][N], marked in `fresh`); *count gets
+// the number of such nodes.  launch_grow_commit copies them into d / rot
+// and marks them known.
+template <typename T>
+hipError_t launch_grow_layer(const LevelView<T>& L, const unsigned char* act,
+                             const unsigned char* known, T* tmp_d, T* tmp_r,
+                             unsigned char* fresh, int* count, hipStream_t s);
+template <typename T>
+hipError_t launch_grow_commit(const LevelView<T>& L, const T* tmp_d, const T* tmp_r,
+                              unsigned char* fresh, unsigned char* known, hipStream_t s);
 
 template <typename T>
 hipError_t launch_assemble_nodes(const LevelView<T>& L, const RowView<T>& R, const int* flags,
@@ -217,6 +241,7 @@ inline Dispatch<T> single(const LevelView<T>& L, int blocks) {
   D.starts = nullptr;
   D.n = 1;
   D.blocks = blocks;
+  D.masked = L.act != nullptr;
   return D;
 }
 

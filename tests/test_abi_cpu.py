@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vd.h")
 HEADERS = [HEADER, os.path.join(ROOT, "include", "vd_net.h"),
-           os.path.join(ROOT, "include", "vd_track.h")]
+           os.path.join(ROOT, "include", "vd_track.h"), os.path.join(ROOT, "include", "vd_fusion.h")]
 
 
 def _declared():
