@@ -54,12 +54,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tile: int, name: str = "traffic_k_cg_frame64.md"):
-    """HBM bytes per launch of the 64^3 CG-iteration kernel with stencil tile
-    `tile` (1..7) from the committed rocprofv3 counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by the same counters on a plain copy), or None if the
-    summary is missing, has no entry for that tile, or the kernel's sources
-    changed since the counters were taken."""
+def measured_traffic(key: str, name: str = "traffic_k_cg_frame64.md"):
+    """HBM bytes per launch of a CG-iteration kernel from a committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy), e.g. key "tile7" for the 64^3 kernel with
+    stencil tile 7; None if the summary is missing, has no such entry, or the
+    kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -72,9 +72,22 @@ def measured_traffic(tile: int, name: str = "traffic_k_cg_frame64.md"):
     if kv.get("source_sha") != kernel_source_sha():
         return None
     try:
-        return float(kv[f"traffic_bytes_per_launch_tile{tile}"])
+        return float(kv[f"traffic_bytes_per_launch_{key}"])
     except (KeyError, ValueError):
         return None
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 def copy_probe(mib: int = 1024, reps: int = 3) -> int:
@@ -110,6 +123,9 @@ def main() -> int:
                     help="frames of the held-out sequence in the warm-vs-plain leg")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent launch per CG solve on levels of <= 128 tiles")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time the main workload only (no tracked-frame, active-set or "
+                         "warm-vs-plain legs): the byte-counter runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (byte-counter calibration)")
     args = ap.parse_args()
@@ -118,6 +134,8 @@ def main() -> int:
     # the warm-vs-plain leg generates its held-out frames in worker processes,
     # started before this process first touches the GPU
     pool = None
+    if args.main_only:
+        args.no_warm = True
     if args.workload == "frame64" and not args.no_warm:
         from paper_1603_08161_amd import warm
         pool = warm.make_pool(min(8, os.cpu_count() or 1))
@@ -203,12 +221,15 @@ def main() -> int:
             t_cpu = time.perf_counter() - tc
         e_ref = float(ref["energy"][0])
         out_cpu = {"value": 1.0 / t_cpu, "unit": "frames/s", "cores": 1, "kind": "oracle",
+                   "host_cpu": host_cpu_model(), "host_nproc": os.cpu_count(),
                    "sample": "one full frame of the same workload (3 levels x 8 GN x 20 PCG, "
                              f"FP64, single-threaded BLAS): {t_cpu:.2f} s"}
         print(f"# oracle: {t_cpu:.2f} s/frame, E = {e_ref:.9g}", flush=True)
 
-    track_leg = tracked_frame_leg(args, tiles)
-    active_leg = active_set_leg(args, scene, inputs)
+    track_leg = active_leg = None
+    if not args.main_only:
+        track_leg = tracked_frame_leg(args, tiles)
+        active_leg = active_set_leg(args, scene, inputs)
 
     warm_leg = None
     if not args.no_warm:
@@ -261,12 +282,15 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(tiles[-1]),
+            "traffic": measured_traffic(f"tile{tiles[-1]}"),
             "bytes_per_launch": nbytes,
             "mean_us": cg_a_us,
             "timing": "device clock stamps captured in the frame graph around the 64^3 "
                       "level's CG iterations 1..19 of each flip-flop iteration, last timed "
                       "replay (rocprofv3 kernel-trace mean in profiles/k_cg_frame64.md)",
+            "note": "effective bandwidth: the 64^3 level's ~40 MB per launch stays in the "
+                    "256 MB last-level cache (MALL) across iterations; the HBM-bound case is "
+                    "--workload batch32 (~530 MB per launch)",
         },
         "kernel_mean_us_eager": prof_us,
         "cpu_baseline": out_cpu,
@@ -543,8 +567,12 @@ def bench_batch(args) -> int:
         "roofline": {"bound": "hbm", "kernel": "batched fused CG iteration (k_cg_occ<float>) "
                                                "on the finest level of the float32 lattices",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": nbytes, "mean_us": cg_us},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("batch_f32", "traffic_k_cg_batch32.md"),
+                     "bytes_per_launch": nbytes, "mean_us": cg_us,
+                     "timing": "profiled eager batch of the float32 lattices, stream events "
+                               "around each launch (rocprofv3 kernel-trace mean in "
+                               "profiles/traffic_k_cg_batch32.md)"},
         "kernel_mean_us": prof_us,
     }
     print(json.dumps(line), flush=True)
