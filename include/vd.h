@@ -175,7 +175,11 @@ typedef struct {
  * state.  When energy_target > 0 the call runs finest-level flip-flop
  * iterations only, and stops after the first one whose energy is <=
  * energy_target, or after max_gn of them; with energy_target == 0 the full
- * schedule runs.  Target mode waits for the stream after every iteration. */
+ * schedule runs.  Target mode decides on the device: every launch of an
+ * iteration returns at entry once an earlier iteration has reached the
+ * target.  The call queues as many iterations as its previous target-mode
+ * call needed, waits for the stream, and then adds one iteration per wait
+ * until the target is reached or max_gn iterations are queued. */
 typedef struct {
   int32_t reset_to_rest;    /* start from t = t_hat, R = I instead of the
                                previous frame's state */

@@ -1263,30 +1263,40 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
-  // One flip-flop iteration on the finest level followed by the energy.
-  int enqueue_gn_finest(hipStream_t s) {
+  // One finest-level flip-flop iteration; with `stop` every launch is
+  // guarded by the device flag and the iteration ends with the target check.
+  int enqueue_gn_finest(hipStream_t s, const int* stop = nullptr) {
     const LevelView<T> V = finest().view(desc_.w_arap);
     const int pcg = desc_.pcg_iters[L_ - 1];
-    VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s));
+    auto g = [&](const Dispatch<T>& D) { return guarded(D, stop); };
+    VD_TRY(launch_stencil<T>(kModeRhs, g(tiles_of(V)), nullptr, nullptr, s));
     if (persistent(finest()) && pcg > 0) {
-      VD_TRY(launch_cg_loop<T>(pcg, tiles_of(V), s));
+      VD_TRY(launch_cg_loop<T>(pcg, g(tiles_of(V)), s));
     } else {
-      for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), s));
-      if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, nodes_of(V), s));
+      for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, g(tiles_of(V)), s));
+      if (pcg > 0) VD_TRY(launch_cg_final<T>(pcg - 1, g(nodes_of(V)), s));
     }
-    VD_TRY(launch_polar<T>(nodes_of(V), s));
-    VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, s));
+    VD_TRY(launch_polar<T>(g(nodes_of(V)), s));
+    VD_TRY(launch_energy<T>(g(energy_of(V)), g(one_of(V)), 0, s));
+    if (stop) VD_TRY(launch_target_step(V.sc, s));
     return VD_OK;
   }
 
-  // Target mode: finest-level iterations until E <= target or `cap` of them.
+  // Target mode: finest-level iterations until E <= target or `cap` of them,
+  // decided on the device.  Every launch of an iteration is guarded by the
+  // stop flag that the target check sets, so iterations queued beyond the
+  // one that reaches the target cost only their empty launches.  The host
+  // queues the previous call's iteration count at once (one graph launch per
+  // iteration with VD_FLAG_GRAPH), waits, and then adds one iteration per
+  // wait until the flag is set or `cap` are queued: one wait per frame when
+  // consecutive frames need the same count, without paying for `cap` empty
+  // iterations when the target comes early.
   int run_target(double target, int cap, int* done, int* reached) {
     const LevelView<T> V = finest().view(desc_.w_arap);
+    const int* stop = &V.sc->stop;
     VD_TRY(launch_reset_counters<T>(one_of(V), stream_));
-    double e = 0.0;
-    VD_CHECK(finest_energy(&e));
-    *done = 0;
-    *reached = e <= target ? 1 : 0;
+    VD_TRY(launch_energy<T>(energy_of(V), one_of(V), 0, stream_));
+    VD_TRY(launch_target_begin(V.sc, target, stream_));
     const bool graph = (desc_.flags & VD_FLAG_GRAPH) != 0;
     if (graph && (gn_graph_gen_ != alloc_gen_ || !gn_graph_)) {
       if (gn_graph_) {
@@ -1295,31 +1305,40 @@ class Solver final : public ISolver {
       }
       if (!capture_stream_)
         VD_TRY(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
-      hipGraph_t g = nullptr;
+      hipGraph_t gr = nullptr;
       VD_TRY(hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal));
-      const int rc = enqueue_gn_finest(capture_stream_);
-      const hipError_t ec = hipStreamEndCapture(capture_stream_, &g);
+      const int rc = enqueue_gn_finest(capture_stream_, stop);
+      const hipError_t ec = hipStreamEndCapture(capture_stream_, &gr);
       if (rc != VD_OK) {
-        if (g) (void)hipGraphDestroy(g);
+        if (gr) (void)hipGraphDestroy(gr);
         return rc;
       }
       if (ec != hipSuccess) return VD_EHIP;
-      const hipError_t ei = hipGraphInstantiate(&gn_graph_, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
+      const hipError_t ei = hipGraphInstantiate(&gn_graph_, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
       if (ei != hipSuccess) return VD_EHIP;
       gn_graph_gen_ = alloc_gen_;
     }
-    while (!*reached && *done < cap) {
-      if (graph) {
-        VD_TRY(hipGraphLaunch(gn_graph_, stream_));
-      } else {
-        VD_CHECK(enqueue_gn_finest(stream_));
+    int queued = 0;
+    int chunk = std::min(std::max(target_hint_, 1), cap);
+    while (queued < cap) {
+      for (int k = 0; k < chunk; ++k) {
+        if (graph) VD_TRY(hipGraphLaunch(gn_graph_, stream_));
+        else VD_CHECK(enqueue_gn_finest(stream_, stop));
       }
+      queued += chunk;
       VD_TRY(hipMemcpyAsync(h_sc_, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
       VD_TRY(hipStreamSynchronize(stream_));
-      ++*done;
-      if (h_sc_->energy[0] <= target) *reached = 1;
+      if (h_sc_->stop) break;
+      chunk = 1;
     }
+    if (cap == 0) {
+      VD_TRY(hipMemcpyAsync(h_sc_, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+    }
+    *done = h_sc_->gn_done;
+    *reached = h_sc_->energy[0] <= target ? 1 : 0;
+    target_hint_ = *done;
     return VD_OK;
   }
 
@@ -1532,8 +1551,9 @@ class Solver final : public ISolver {
   int n_stamped_ = 0, stamped_launches_ = 0;
   // warm start
   T *warm_d_ = nullptr, *warm_rot_ = nullptr;  // plain initialisation kept for the judge
-  hipGraphExec_t gn_graph_ = nullptr;          // one finest-level iteration (target mode)
+  hipGraphExec_t gn_graph_ = nullptr;          // one guarded finest-level iteration
   long gn_graph_gen_ = -1;
+  int target_hint_ = 0;  // iterations the last target-mode call needed
   float* feat_scratch_ = nullptr;  // per-row residual pieces of the features
   size_t feat_cap_ = 0;
   uint16_t* feat_x_ = nullptr;     // features staged for a host copy

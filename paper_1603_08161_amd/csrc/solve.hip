@@ -31,6 +31,9 @@ struct Where {
   int b, local, count;
 };
 
+// The lattice is the number of b in 1..n-1 with starts[b] <= g (starts is
+// non-decreasing): one wave-wide vector load and ballot per 64 lattices
+// instead of a binary search's chain of dependent loads.
 template <typename T>
 __device__ __forceinline__ Where<T> locate(const Dispatch<T>& D, int g) {
   Where<T> w;
@@ -41,17 +44,26 @@ __device__ __forceinline__ Where<T> locate(const Dispatch<T>& D, int g) {
     w.count = D.blocks;
     return w;
   }
-  int lo = 0, hi = D.n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (D.starts[mid] <= g) lo = mid;
-    else hi = mid;
+  const int lane = threadIdx.x & (kWave - 1);
+  int lo = 0;
+  for (int base = 1; base < D.n; base += kWave) {
+    const int idx = base + lane;
+    lo += __popcll(__ballot(idx < D.n && D.starts[idx] <= g));
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);
   w.L = D.views[lo];
   w.b = lo;
   w.local = g - D.starts[lo];
   w.count = D.starts[lo + 1] - D.starts[lo];
   return w;
+}
+
+// A guarded launch (energy-target mode) returns at entry once the target
+// was reached: the flag is uniform, so every workgroup leaves before any
+// barrier or store.
+template <typename T>
+__device__ __forceinline__ bool skipped(const Dispatch<T>& D) {
+  return D.stop != nullptr && *D.stop != 0;
 }
 
 template <typename T>
@@ -301,6 +313,7 @@ __device__ __forceinline__ void eval_data_nodes(const LevelView<T>& L,
 template <typename T, typename TL, int MODE, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __restrict__ pin,
                                                     T* __restrict__ out) {
+  if (skipped(D)) return;
   __shared__ T sp[3][TL::HALO];
   __shared__ unsigned char sm[TL::HALO];
   __shared__ DataShare<T, TL> ds;
@@ -712,6 +725,7 @@ __device__ __forceinline__ void entry_stamp(unsigned long long* stamp) {
 
 template <typename T, typename TL, bool FIRST, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m, unsigned long long* stamp) {
+  if (skipped(D)) return;
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   __shared__ unsigned char sm[TL::HALO];
@@ -728,6 +742,7 @@ __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m, unsigned lo
 template <typename T, typename TL, bool FIRST, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m,
                                                    unsigned long long* stamp) {
+  if (skipped(D)) return;
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   __shared__ unsigned char sm[TL::HALO];
@@ -792,6 +807,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
 // All iterations of one CG solve (single lattice, every tile resident).
 template <typename T, typename TL, bool MASK>
 __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
+  if (skipped(D)) return;
   __shared__ T sp[3][TL::HALO];
   __shared__ T sr[3][TL::HALO];
   __shared__ unsigned char sm[TL::HALO];
@@ -812,6 +828,7 @@ __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
                                                      unsigned long long* stamp) {
+  if (skipped(D)) return;
   entry_stamp(stamp);
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
@@ -900,6 +917,7 @@ hipError_t launch_cg_loop(int iters, const Dispatch<T>& D, hipStream_t s) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_energy(Dispatch<T> D) {
+  if (skipped(D)) return;
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
   double part[3] = {0.0, 0.0, 0.0};
@@ -971,6 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dispatch<T> D) {
 // One workgroup per lattice: sums its energy partials into sc->energy.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_energy_finalize(Dispatch<T> D1, int record_trace) {
+  if (skipped(D1)) return;
   const LevelView<T> L = view_of(D1, blockIdx.x);
   const int n = energy_blocks_dev(L);
   double v[3];
@@ -1010,6 +1029,29 @@ __global__ void k_reset_counters(Dispatch<T> D1) {
   sc->bar_timeouts = 0;
 }
 
+__global__ void k_target_begin(Scalars* sc, double target) {
+  if (threadIdx.x != 0) return;
+  sc->target = target;
+  sc->gn_done = 0;
+  sc->stop = sc->energy[0] <= target ? 1 : 0;
+}
+
+__global__ void k_target_step(Scalars* sc) {
+  if (threadIdx.x != 0 || sc->stop) return;
+  sc->gn_done += 1;
+  if (sc->energy[0] <= sc->target) sc->stop = 1;
+}
+
+hipError_t launch_target_begin(Scalars* sc, double target, hipStream_t s) {
+  k_target_begin<<<1, 64, 0, s>>>(sc, target);
+  return hipGetLastError();
+}
+
+hipError_t launch_target_step(Scalars* sc, hipStream_t s) {
+  k_target_step<<<1, 64, 0, s>>>(sc);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_reset_counters(const Dispatch<T>& D1, hipStream_t s) {
   k_reset_counters<T><<<D1.blocks, 64, 0, s>>>(D1);
@@ -1022,6 +1064,7 @@ hipError_t launch_reset_counters(const Dispatch<T>& D1, hipStream_t s) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_polar(Dispatch<T> D) {
+  if (skipped(D)) return;
   const Where<T> w = locate(D, blockIdx.x);
   const LevelView<T>& L = w.L;
   const int i = w.local * kBlock + threadIdx.x;

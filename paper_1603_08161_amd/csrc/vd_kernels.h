@@ -35,6 +35,11 @@ struct Scalars {
   int n_dense;     // dense rows among them
   unsigned bar;      // arrivals at the grid barrier of the persistent CG loop
   int bar_timeouts;  // grid barrier waits that gave up (bounded spin)
+  // energy-target mode: the target, set once E_total <= target (every
+  // guarded launch then returns at entry), and iterations completed
+  double target;
+  int stop;
+  int gn_done;
   double trace[VD_MAX_TRACE];
 };
 
@@ -91,6 +96,7 @@ struct Dispatch {
   int n;
   int blocks;                 // total workgroups
   int masked;                 // some lattice restricts the solve to its set M
+  const int* stop;            // non-null: return at entry while *stop is set
 };
 
 // Constraint rows of one level (dense rows then 3 rows per sparse pair).
@@ -244,6 +250,21 @@ inline Dispatch<T> single(const LevelView<T>& L, int blocks) {
   D.masked = L.act != nullptr;
   return D;
 }
+
+// The same launch, skipped on the device while *stop is set (the launches
+// of an energy-target iteration).
+template <typename T>
+inline Dispatch<T> guarded(Dispatch<T> D, const int* stop) {
+  D.stop = stop;
+  return D;
+}
+
+// Energy-target mode on the device: begin sets sc->target, clears the
+// iteration count and sets sc->stop if E_total (sc->energy[0], just
+// evaluated) is already <= target; step, after each guarded iteration that
+// ran, counts it and sets sc->stop once E_total <= target.
+hipError_t launch_target_begin(Scalars* sc, double target, hipStream_t s);
+hipError_t launch_target_step(Scalars* sc, hipStream_t s);
 
 // flags |= 1 where any of the n floats is not finite.
 hipError_t launch_check_finite(const float* v, int64_t n, int* flags, hipStream_t s);

@@ -271,7 +271,7 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
                              gn_warm=rw["gn_done"], reached_warm=rw["target_reached"],
                              e_warm=float(rw["energy"][0]), t_warm_ms=1e3 * t_warm,
                              gn_plain_target=rp["gn_done"], reached_plain=rp["target_reached"],
-                             t_plain_target_ms=1e3 * t_pt,
+                             t_plain_target_ms=1e3 * t_pt, e_plain_target=float(rp["energy"][0]),
                              e_init_cv=rc["init_energy"][1], cv_used=rc["warm_used"],
                              gn_cv=rc["gn_done"], reached_cv=rc["target_reached"],
                              pred_mse=net_err,
@@ -309,6 +309,12 @@ def summarise(recs: List[Dict]) -> Dict:
         pred_mse_mean=float(np.mean(a("pred_mse"))),
         cv_mse_mean=float(np.mean(a("cv_mse"))),
         zero_mse_mean=float(np.mean(a("zero_mse"))),
+        # the warm start's own factor: the same stopping rule from the plain
+        # initialisation over the judged prediction (> 1: the network helps)
+        warm_start_factor=float(np.mean(a("t_plain_target_ms")) / np.mean(a("t_warm_ms"))),
+        warm_start_gn_factor=float(np.mean(a("gn_plain_target")) / max(np.mean(a("gn_warm")), 1e-9)),
+        # the plain schedule over the warm path: credits the energy-target
+        # stopping rule as much as the network
         speedup_vs_plain_schedule=float(np.mean(a("t_plain_ms")) / np.mean(a("t_warm_ms"))),
     )
 
