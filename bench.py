@@ -210,6 +210,17 @@ def main() -> int:
           f"{graph_n['cg_a']} launches; eager finest-level kernel means (us): "
           + ", ".join(f"{k}={v:.2f}" for k, v in prof_us.items()), flush=True)
 
+    # the constraint build alone (part of every timed step): validation,
+    # rows, the radix sort by cell, segments, cell cache and node blocks of
+    # the three levels
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for _ in range(10):
+        lat.set_constraints(*inputs)
+    torch.cuda.synchronize()
+    set_constraints_ms = (time.perf_counter() - tc) * 1e2
+    print(f"# set_constraints: {set_constraints_ms:.3f} ms per frame", flush=True)
+
     out_cpu = None
     e_ref = None
     if not args.no_oracle:
@@ -293,6 +304,7 @@ def main() -> int:
                     "--workload batch32 (~530 MB per launch)",
         },
         "kernel_mean_us_eager": prof_us,
+        "set_constraints_ms": set_constraints_ms,
         "cpu_baseline": out_cpu,
         "tracked_frame": track_leg,
         "active_set": active_leg,

@@ -347,6 +347,19 @@ int vd_debug_rotations(vd_lattice* l, int32_t level, const float* pos, const flo
 int vd_debug_fit_rotations(const float* M, const float* R_prev, float* R, int32_t* keep,
                            int64_t n, int32_t precision, int32_t mem, void* stream);
 
+/* The library's stable radix sort of n (key, value) pairs by the low end_bit
+ * bits of the keys (0 <= end_bit <= 32; the higher bits must be zero), equal
+ * keys keeping their input order: keys_out, vals_out [n].  The binning of
+ * constraint rows by cell (Sec. 7.1).  Synchronous, on `stream`. */
+int vd_debug_sort_pairs(const uint32_t* keys, const int32_t* vals, uint32_t* keys_out,
+                        int32_t* vals_out, int64_t n, int32_t end_bit, int32_t mem,
+                        void* stream);
+
+/* The library's exclusive prefix sum of n int32 values: out[i] = sum of
+ * in[0 .. i).  Synchronous, on `stream`. */
+int vd_debug_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t mem,
+                            void* stream);
+
 /* Prolongation of a coarse per-node field (level-1) to `level`: out[3N_fine]
  * = trilinear evaluation of coarse[3N_coarse] at the fine rest positions.
  * Synchronous. */

@@ -18,6 +18,8 @@ from ._lib import (  # noqa: F401
     rigid_pose_noalloc,
     VDError,
     fit_rotations,
+    sort_pairs,
+    exclusive_scan,
     lib,
     strerror,
     VD_OK, VD_EINVAL, VD_ERANGE, VD_ENOMEM, VD_EHIP, VD_ESTATE,

@@ -51,6 +51,7 @@ EXPORTED = (
     "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
     "vd_set_pose", "vd_track_frame", "vd_debug_associate", "vd_rigid_pose_noalloc",
     "vd_get_active", "vd_fuse_depth", "vd_get_tsdf", "vd_set_tsdf", "vd_extract_mesh",
+    "vd_debug_sort_pairs", "vd_debug_exclusive_scan",
 )
 VD_TRACK_MAX_ITERS = 64
 VD_NOALLOC_MAX_SAMPLES = 1 << 30
@@ -218,6 +219,8 @@ def _load() -> C.CDLL:
         "vd_debug_diag": ([vp, i32, vp, i32], C.c_int),
         "vd_debug_rotations": ([vp, i32, vp, vp, vp, i32], C.c_int),
         "vd_debug_fit_rotations": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
+        "vd_debug_sort_pairs": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
+        "vd_debug_exclusive_scan": ([vp, vp, i64, i32, vp], C.c_int),
         "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
         "vd_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
         "vd_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
@@ -780,6 +783,31 @@ def fit_rotations(M, R_prev=None, precision: str = "fp32", stream: Optional[int]
                                        VD_FP64 if precision == "fp64" else VD_FP32_FP64RED,
                                        VD_MEM_HOST, C.c_void_p(s)), "vd_debug_fit_rotations")
     return R.reshape(n, 3, 3), code
+
+
+def sort_pairs(keys, vals, end_bit: int, stream: Optional[int] = None):
+    """The library's stable radix sort by the low end_bit key bits (host
+    arrays): returns (sorted keys, values in the same order)."""
+    k = np.ascontiguousarray(keys, np.uint32).ravel()
+    v = np.ascontiguousarray(vals, np.int32).ravel()
+    if k.shape != v.shape:
+        raise ValueError("keys and vals must have the same length")
+    ko, vo = np.empty_like(k), np.empty_like(v)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_debug_sort_pairs(k.ctypes.data, v.ctypes.data, ko.ctypes.data, vo.ctypes.data,
+                                    k.size, int(end_bit), VD_MEM_HOST, C.c_void_p(s)),
+           "vd_debug_sort_pairs")
+    return ko, vo
+
+
+def exclusive_scan(values, stream: Optional[int] = None):
+    """The library's exclusive prefix sum of int32 values (host arrays)."""
+    x = np.ascontiguousarray(values, np.int32).ravel()
+    out = np.empty_like(x)
+    s = _current_stream() if stream is None else stream
+    _check(_lib.vd_debug_exclusive_scan(x.ctypes.data, out.ctypes.data, x.size, VD_MEM_HOST,
+                                        C.c_void_p(s)), "vd_debug_exclusive_scan")
+    return out
 
 
 def _bf16_ptr(x, n, what):

@@ -2084,6 +2084,88 @@ int vd_debug_prolong(vd_lattice* l, int32_t level, const float* coarse, float* o
   return l->impl->debug_prolong(level, coarse, out, mem);
 }
 
+namespace {
+
+// Device copies of a debug entry's host arguments (freed on scope exit).
+struct DebugBuffers {
+  std::vector<void*> bufs;
+  ~DebugBuffers() {
+    for (void* b : bufs) (void)hipFree(b);
+  }
+  void* get(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes > 0 ? bytes : 1) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return p;
+  }
+};
+
+}  // namespace
+
+int vd_debug_sort_pairs(const uint32_t* keys, const int32_t* vals, uint32_t* keys_out,
+                        int32_t* vals_out, int64_t n, int32_t end_bit, int32_t mem,
+                        void* stream) {
+  if (n < 0 || n > INT32_MAX || end_bit < 0 || end_bit > 32) return VD_EINVAL;
+  if (n > 0 && (!keys || !vals || !keys_out || !vals_out)) return VD_EINVAL;
+  if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+  if (n == 0) return VD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  DebugBuffers db;
+  const size_t bytes = 4 * (size_t)n;
+  const size_t tb = vd::sort_temp_bytes((int)n);
+  void* temp = db.get(tb);
+  if (!temp) return VD_ENOMEM;
+  const unsigned* kin = keys;
+  const int* vin = vals;
+  unsigned* kout = keys_out;
+  int* vout = vals_out;
+  if (mem == VD_MEM_HOST) {
+    void *a = db.get(bytes), *b = db.get(bytes), *c = db.get(bytes), *d = db.get(bytes);
+    if (!a || !b || !c || !d) return VD_ENOMEM;
+    if (hipMemcpyAsync(a, keys, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b, vals, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+      return VD_EHIP;
+    kin = (const unsigned*)a;
+    vin = (const int*)b;
+    kout = (unsigned*)c;
+    vout = (int*)d;
+  }
+  hipError_t e = vd::sort_pairs(temp, tb, kin, kout, vin, vout, (int)n, end_bit, s);
+  if (e == hipSuccess && mem == VD_MEM_HOST) {
+    e = hipMemcpyAsync(keys_out, kout, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(vals_out, vout, bytes, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? VD_OK : VD_EHIP;
+}
+
+int vd_debug_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t mem,
+                            void* stream) {
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!in || !out))) return VD_EINVAL;
+  if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+  if (n == 0) return VD_OK;
+  hipStream_t s = (hipStream_t)stream;
+  DebugBuffers db;
+  const size_t bytes = 4 * (size_t)n;
+  const size_t tb = vd::scan_temp_bytes((int)n);
+  void* temp = db.get(tb);
+  if (!temp) return VD_ENOMEM;
+  const int* din = in;
+  int* dout = out;
+  if (mem == VD_MEM_HOST) {
+    void *a = db.get(bytes), *b = db.get(bytes);
+    if (!a || !b) return VD_ENOMEM;
+    if (hipMemcpyAsync(a, in, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return VD_EHIP;
+    din = (const int*)a;
+    dout = (int*)b;
+  }
+  hipError_t e = vd::exclusive_scan(temp, tb, din, dout, (int)n, s);
+  if (e == hipSuccess && mem == VD_MEM_HOST)
+    e = hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? VD_OK : VD_EHIP;
+}
+
 int vd_debug_fit_rotations(const float* M, const float* R_prev, float* R, int32_t* keep,
                            int64_t n, int32_t precision, int32_t mem, void* stream) {
   if (n < 0 || (n > 0 && (!M || !R))) return VD_EINVAL;

@@ -291,7 +291,9 @@ template <typename T>
 hipError_t launch_fit_batch(const float* M, const float* R_prev, float* R, int* keep, int64_t n,
                             hipStream_t s);
 
-// rocPRIM-backed primitives (separate translation unit).
+// Stable radix sort of (key, value) pairs by the low end_bit bits of the
+// keys and exclusive integer prefix sums (sort.hip); temp holds at least
+// sort_temp_bytes / scan_temp_bytes bytes.
 size_t sort_temp_bytes(int n);
 hipError_t sort_pairs(void* temp, size_t bytes, const unsigned* kin, unsigned* kout,
                       const int* vin, int* vout, int n, int end_bit, hipStream_t s);
