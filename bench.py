@@ -482,6 +482,10 @@ def bench_batch(args) -> int:
     for lat, inp in zip(lats, inputs):
         lat.set_constraints(*inp)
     batch = Batch(lats)
+    # tile autotuning of the batched launches (setup, outside the timed
+    # region): per precision part and level, the fastest tile kind
+    batch_tiles, _ = batch.tune(iters=10)
+    print(f"# batch tiles per level {batch_tiles}", flush=True)
 
     def step():
         for lat, inp in zip(lats, inputs):
@@ -499,10 +503,10 @@ def bench_batch(args) -> int:
     elapsed = time.perf_counter() - t0
     print(f"# timed {args.steps} batch frames in {elapsed * 1e3:.2f} ms", flush=True)
 
-    # the float32 part alone, profiled eagerly (same tile choice as in the
-    # timed batch: the largest float32 lattice's default per level)
+    # the float32 part alone, profiled eagerly with the tuned tiles
     f32 = [k for k, p in enumerate(precs) if p == "fp32"]
-    prof_lats = [Lattice.from_spec(scenes[k].spec, profile=True) for k in f32]
+    prof_lats = [Lattice.from_spec(scenes[k].spec, profile=True,
+                                   tiles=tuple(batch_tiles["fp32"])) for k in f32]
     for lat, k in zip(prof_lats, f32):
         lat.set_constraints(*inputs[k])
     pb = Batch(prof_lats)
@@ -574,13 +578,15 @@ def bench_batch(args) -> int:
                    "n_dense": sum(s.n_dense for s in scenes),
                    "precision": precs,
                    "launch": "one launch per schedule step over the lattices of each "
-                             "precision, hipGraph; the float64 part on a forked stream"},
+                             "precision, hipGraph; the float64 part on a forked stream",
+                   "tiles": batch_tiles},
         "oracle_gate": gate,
         "roofline": {"bound": "hbm", "kernel": "batched fused CG iteration (k_cg_occ<float>) "
                                                "on the finest level of the float32 lattices",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("batch_f32", "traffic_k_cg_batch32.md"),
+                     "traffic": measured_traffic(f"batch_f32_tile{batch_tiles['fp32'][-1]}",
+                                                 "traffic_k_cg_batch32.md"),
                      "bytes_per_launch": nbytes, "mean_us": cg_us,
                      "timing": "profiled eager batch of the float32 lattices, stream events "
                                "around each launch (rocprofv3 kernel-trace mean in "

@@ -260,6 +260,17 @@ int vd_batch_create(vd_lattice* const* lattices, int32_t n, vd_batch** out);
  * opts applies; a warm start or energy target gives VD_EINVAL. */
 int vd_batch_solve(vd_batch* b, const vd_solve_opts* opts, double* energies);
 
+/* Tile autotuner of the batch (as vd_tune, over the batched launches): per
+ * part (float32 lattices, then float64 ones) and level, times one batched
+ * position step (gradient pass and `iters` CG iterations) from the current
+ * state with every tile kind, keeps the fastest for every handle of the part
+ * and restores the displacements.  tile_out[2 * VD_MAX_LEVELS] (may be NULL)
+ * receives the chosen kinds (1-based; 0 for a missing part), us_out[2 *
+ * VD_MAX_LEVELS * VD_TILE_KINDS] (may be NULL) the microseconds per CG
+ * iteration, gradient pass included, of every (part, level, kind).
+ * VD_ESTATE if a handle has no constraints.  Waits for the stream. */
+int vd_batch_tune(vd_batch* b, int32_t iters, int32_t* tile_out, double* us_out);
+
 /* Mean duration (us) and count of the finest level's launches per kernel
  * class (VD_PROF_*) of the last batch frame, when the first handle was
  * created with VD_FLAG_PROFILE and without VD_FLAG_GRAPH (zeros otherwise).

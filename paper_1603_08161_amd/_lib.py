@@ -51,7 +51,7 @@ EXPORTED = (
     "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
     "vd_set_pose", "vd_track_frame", "vd_debug_associate", "vd_rigid_pose_noalloc",
     "vd_get_active", "vd_fuse_depth", "vd_get_tsdf", "vd_set_tsdf", "vd_extract_mesh",
-    "vd_debug_sort_pairs", "vd_debug_exclusive_scan",
+    "vd_debug_sort_pairs", "vd_debug_exclusive_scan", "vd_batch_tune",
 )
 VD_TRACK_MAX_ITERS = 64
 VD_NOALLOC_MAX_SAMPLES = 1 << 30
@@ -221,6 +221,7 @@ def _load() -> C.CDLL:
         "vd_debug_fit_rotations": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
         "vd_debug_sort_pairs": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
         "vd_debug_exclusive_scan": ([vp, vp, i64, i32, vp], C.c_int),
+        "vd_batch_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
         "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
         "vd_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
         "vd_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
@@ -686,6 +687,21 @@ class Batch:
         n = (C.c_int32 * VD_PROF_KINDS)()
         _check(_lib.vd_batch_profile(self._h, us, n), "vd_batch_profile")
         return {PROF_NAMES[k]: float(us[k]) for k in range(len(PROF_NAMES)) if n[k] > 0}
+
+    def tune(self, iters: int = 10):
+        """Batch tile autotuner (vd_batch_tune): returns ({"fp32": tiles per
+        level, "fp64": ...} for the parts present, us per CG iteration with
+        the gradient pass included [part][level][kind])."""
+        tiles = (C.c_int32 * (2 * VD_MAX_LEVELS))()
+        us = (C.c_double * (2 * VD_MAX_LEVELS * VD_TILE_KINDS))()
+        _check(_lib.vd_batch_tune(self._h, int(iters), tiles, us), "vd_batch_tune")
+        out = {}
+        for k, name in enumerate(("fp32", "fp64")):
+            t = [int(tiles[k * VD_MAX_LEVELS + l]) for l in range(VD_MAX_LEVELS)]
+            if any(t):
+                out[name] = [x for x in t if x]
+        u = np.array(us[:]).reshape(2, VD_MAX_LEVELS, VD_TILE_KINDS)
+        return out, u
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

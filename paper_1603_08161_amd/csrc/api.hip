@@ -931,6 +931,7 @@ class Solver final : public ISolver {
   hipStream_t stream() const { return stream_; }
   bool has_constraints() const { return have_constraints_; }
   void mark_energy_fresh() { energy_fresh_ = true; }
+  void mark_energy_stale() { energy_fresh_ = false; }
   const vd_lattice_desc& desc() const { return desc_; }
   int level_nodes(int l) const { return lv_[l].N; }
   int level_tile(int l) const { return lv_[l].tile; }
@@ -1602,6 +1603,8 @@ class IBatch {
   // Final energies (4 per lattice) after the frame finished.
   virtual int energies(double* e) = 0;
   virtual int profile(double* us, int* n) = 0;
+  // Tile autotuner over the batched launches (see vd_batch_tune).
+  virtual int tune(int iters, hipStream_t s, int* tile_out, double* us_out) = 0;
 };
 
 template <typename T>
@@ -1735,6 +1738,78 @@ class Batch final : public IBatch {
   }
 
   int profile(double* us, int* n) override { return timer_.collect(us, n); }
+
+  // Per level, every tile kind for all lattices of this part, timed over one
+  // batched position step (the gradient pass and `iters` CG iterations) from
+  // the lattices' current state; the fastest kind is kept and the lattices'
+  // displacements are restored.  The fastest of three timings after a
+  // warm-up counts, as in the single-lattice tuner.
+  int tune(int iters, hipStream_t s, int* tile_out, double* us_out) override {
+    if (iters < 1) return VD_EINVAL;
+    for (auto* h : h_)
+      if (!h->has_constraints()) return VD_ESTATE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VD_TRY(hipEventCreate(&e0));
+    VD_TRY(hipEventCreate(&e1));
+    int rc = VD_OK;
+    for (int l = 0; l < L_ && rc == VD_OK; ++l) {
+      std::vector<T*> saved(n_, nullptr);
+      std::vector<size_t> len(n_, 0);
+      for (int b = 0; b < n_ && rc == VD_OK; ++b) {
+        len[b] = 3 * (size_t)h_[b]->level_nodes(l);
+        rc = pool_.alloc(&saved[b], len[b]);
+        if (rc == VD_OK)
+          rc = hipMemcpyAsync(saved[b], h_[b]->level_view(l).d, len[b] * sizeof(T),
+                              hipMemcpyDeviceToDevice, s) == hipSuccess ? VD_OK : VD_EHIP;
+      }
+      auto restore = [&]() -> int {
+        for (int b = 0; b < n_; ++b)
+          VD_TRY(hipMemcpyAsync(h_[b]->level_view(l).d, saved[b], len[b] * sizeof(T),
+                                hipMemcpyDeviceToDevice, s));
+        return VD_OK;
+      };
+      double best = 1e300;
+      int best_kind = h_[0]->level_tile(l);
+      for (int kind = 0; kind < kTileKinds && rc == VD_OK; ++kind) {
+        for (auto* h : h_) h->force_tile(l, kind);
+        rc = build_tables();
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 4 && rc == VD_OK; ++rep) {
+          float ms = 0.0f;
+          rc = restore();
+          if (rc != VD_OK) break;
+          VD_TRY(hipEventRecord(e0, s));
+          VD_TRY(launch_stencil<T>(kModeRhs, D(l, kTiles), nullptr, nullptr, s));
+          for (int m = 0; m < iters; ++m) VD_TRY(launch_cg<T>(m, D(l, kTiles), s));
+          VD_TRY(hipEventRecord(e1, s));
+          VD_TRY(hipEventSynchronize(e1));
+          VD_TRY(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) best_ms = std::min(best_ms, ms);
+        }
+        const double us = 1000.0 * best_ms / iters;
+        if (us_out) us_out[VD_TILE_KINDS * l + kind] = us;
+        if (us < best) {
+          best = us;
+          best_kind = kind;
+        }
+      }
+      for (auto* h : h_) h->force_tile(l, best_kind);
+      if (tile_out) tile_out[l] = best_kind + 1;
+      if (rc == VD_OK) rc = restore();
+      if (rc == VD_OK) rc = hipStreamSynchronize(s) == hipSuccess ? VD_OK : VD_EHIP;
+      for (T* p : saved) pool_.release(p);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == VD_OK) rc = build_tables();
+    for (auto& g : exec_)  // schedules captured with the old tiles are stale
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    for (auto* h : h_) h->mark_energy_stale();
+    return rc;
+  }
 
   // The frame schedule of Solver::enqueue_frame with every launch batched.
   int enqueue(int reset, hipStream_t s) {
@@ -1979,6 +2054,19 @@ int vd_batch_solve(vd_batch* b, const vd_solve_opts* o, double* energies) {
     if (rc != VD_OK) return rc;
     for (size_t j = 0; j < b->index[k].size(); ++j)
       for (int q = 0; q < 4; ++q) energies[4 * b->index[k][j] + q] = e[4 * j + q];
+  }
+  return VD_OK;
+}
+
+int vd_batch_tune(vd_batch* b, int32_t iters, int32_t* tile_out, double* us_out) {
+  if (!b || iters < 1) return VD_EINVAL;
+  if (tile_out)
+    for (int k = 0; k < 2 * VD_MAX_LEVELS; ++k) tile_out[k] = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (!b->part[k]) continue;
+    const int rc = b->part[k]->tune(iters, b->stream, tile_out ? tile_out + k * VD_MAX_LEVELS : nullptr,
+                                    us_out ? us_out + k * VD_MAX_LEVELS * VD_TILE_KINDS : nullptr);
+    if (rc != VD_OK) return rc;
   }
   return VD_OK;
 }

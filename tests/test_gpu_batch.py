@@ -114,3 +114,33 @@ def test_mixed_precision_batch_equals_individual_solves(graph):
         rep = ref.solve_frame(report=True)
         np.testing.assert_array_equal(e, rep["energy"])
         np.testing.assert_array_equal(lat.get_state()[0], ref.get_state()[0])
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_tuner_keeps_the_state_and_the_bits(graph):
+    """vd_batch_tune (mixed precisions): the state is unchanged by tuning, the
+    chosen tiles are set on every handle of a part, and the tuned batch still
+    equals single solves with those tiles bit for bit."""
+    from paper_1603_08161_amd import Batch
+    scenes = _scenes(gn=2, pcg=6)
+    precs = ["fp64" if k % 2 else "fp32" for k in range(len(scenes))]
+    lats = [make_lattice(s, precision=p, graph=graph) for s, p in zip(scenes, precs)]
+    batch = Batch(lats)
+    batch.solve(reset=True)
+    before = [lat.get_state() for lat in lats]
+    tiles, us = batch.tune(iters=4)
+    print("tuned tiles", tiles, "us/iteration fp32 finest", us[0, 2, :])
+    assert set(tiles) == {"fp32", "fp64"}
+    for name in tiles:
+        assert len(tiles[name]) == 3 and all(1 <= t <= 7 for t in tiles[name])
+    assert np.all(us[0, :3] > 0) and np.all(us[1, :3] > 0)
+    for lat, (p0, r0) in zip(lats, before):
+        p1, r1 = lat.get_state()
+        np.testing.assert_array_equal(p1, p0)
+        np.testing.assert_array_equal(r1, r0)
+    E = batch.solve(reset=True, energies=True)
+    for s, p, lat, e in zip(scenes, precs, lats, E):
+        ref = make_lattice(s, precision=p, tiles=tuple(tiles[p]))
+        rep = ref.solve_frame(reset=True, report=True)
+        np.testing.assert_array_equal(e, rep["energy"])
+        np.testing.assert_array_equal(lat.get_state()[0], ref.get_state()[0])
