@@ -114,15 +114,18 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle (no solved-frame gate, no cpu_baseline)")
-    ap.add_argument("--workload", choices=["frame64", "batch32"], default="frame64",
+    ap.add_argument("--workload", choices=["frame64", "batch32", "net64"], default="frame64",
                     help="frame64: the 64^3 single-frame metric (default); batch32: 32 uneven "
-                         "lattices solved together")
+                         "lattices solved together; net64: the warm-start network at 64^3")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-plain leg (held-out sequence, committed weights)")
     ap.add_argument("--warm-frames", type=int, default=22,
                     help="frames of the held-out sequence in the warm-vs-plain leg")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent launch per CG solve on levels of <= 128 tiles")
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="stencil tile kinds per level, e.g. 1,1,7 (default: the autotuner's "
+                         "choice; fixed tiles make profiled runs time the same kernels)")
     ap.add_argument("--main-only", action="store_true",
                     help="time the main workload only (no tracked-frame, active-set or "
                          "warm-vs-plain legs): the byte-counter runs")
@@ -152,6 +155,8 @@ def main() -> int:
 
     if args.workload == "batch32":
         return bench_batch(args)
+    if args.workload == "net64":
+        return bench_net(args)
 
     scene = make_config1(args.seed)
     spec = scene.spec
@@ -170,11 +175,20 @@ def main() -> int:
     # tile autotuning (setup, outside the timed region): the library times
     # each stencil tile shape per level on these constraints and keeps the
     # fastest for the captured schedule
-    lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent, profile=True)
-    lat.set_constraints(*inputs)
-    tiles, tile_us = lat.tune(iters=10)
-    print(f"# tiles per level {tiles}; us per CG iteration incl. gradient pass [8x8x4, 8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024, 16x4x8/512]: "
-          + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us), flush=True)
+    if args.tiles:
+        tiles = [int(t) for t in args.tiles.split(",")]
+        lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent, profile=True,
+                                tiles=tuple(tiles))
+        lat.set_constraints(*inputs)
+        print(f"# tiles per level {tiles} (fixed)", flush=True)
+    else:
+        lat = Lattice.from_spec(spec, graph=True, persistent=args.persistent, profile=True)
+        lat.set_constraints(*inputs)
+        tiles, tile_us = lat.tune(iters=10)
+        print(f"# tiles per level {tiles}; us per CG iteration incl. gradient pass [8x8x4, "
+              "8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024, 16x4x8/512]: "
+              + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us),
+              flush=True)
 
     def step():
         lat.set_constraints(*inputs)
@@ -592,6 +606,101 @@ def bench_batch(args) -> int:
                                "around each launch (rocprofv3 kernel-trace mean in "
                                "profiles/traffic_k_cg_batch32.md)"},
         "kernel_mean_us": prof_us,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def net_flops(dims, cin0: int = 8) -> float:
+    """Multiply-add flops (2 per MAC) of one forward pass of the warm-start
+    network (include/vd_net.h) on an nx*ny*nz grid: 3x3x3 convolutions at
+    the full, half and quarter resolution (axes halved with rounding up)."""
+    l0 = list(dims)
+    l1 = [(d + 1) // 2 for d in l0]
+    l2 = [(d + 1) // 2 for d in l1]
+    n = [l0[0] * l0[1] * l0[2], l1[0] * l1[1] * l1[2], l2[0] * l2[1] * l2[2]]
+    layers = [(cin0, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2),
+              (64, 32, 1), (64, 32, 1), (32, 16, 0), (32, 16, 0), (16, 3, 0)]
+    return float(sum(2 * 27 * ci * co * n[lv] for ci, co, lv in layers))
+
+
+def bench_net(args) -> int:
+    """The warm-start network (not part of the paper's solve) on the 64^3
+    grid: forward passes (inference, batch 1) and training steps (forward,
+    backward, Adam; batch 4) on synthetic features, against the bfloat16
+    dense matrix-core peak."""
+    import numpy as np
+    import torch
+
+    from paper_1603_08161_amd import Net, warm
+
+    dims = (64, 64, 64)
+    N = dims[0] * dims[1] * dims[2]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    net = Net(dims, max_batch=4)
+    rng = np.random.default_rng(args.seed)
+    if os.path.exists(warm.WEIGHTS):
+        net.set_params(warm.load_weights())
+    else:
+        net.set_params(rng.normal(scale=0.05, size=Net.param_count()).astype(np.float32))
+
+    def bf16_bits(a):
+        u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+        r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+        return torch.from_numpy(r.view(np.int16).reshape(-1)).to(dev)
+
+    # input channels of the size the solver's features have: displacements
+    # and their change (voxels), residual and validity
+    feat = rng.normal(scale=0.2, size=(4, N, 8)).astype(np.float32)
+    feat[..., 7] = (rng.random((4, N)) < 0.1).astype(np.float32)
+    x = bf16_bits(feat)
+    target = torch.from_numpy(rng.normal(scale=0.05, size=4 * 3 * N).astype(np.float32)).to(dev)
+    out = torch.empty(3 * N, dtype=torch.float32, device=dev)
+    x1 = x[: N * 8]
+    for _ in range(max(args.warmup, 1)):
+        net.forward(x1, batch=1, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(x1, batch=1, out=out)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / args.steps
+    params0 = net.get_params()
+    for _ in range(2):
+        net.train_step(x, target, batch=4, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, target, batch=4, lr=1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / args.steps
+    net.set_params(params0)
+    f_fwd = net_flops(dims)
+    achieved = f_fwd / t_fwd / 1e12
+    print(f"# net64: forward {t_fwd * 1e3:.3f} ms ({f_fwd / 1e9:.2f} GFLOP), training step "
+          f"(batch 4) {t_train * 1e3:.3f} ms", flush=True)
+    line = {
+        "metric": "warm-start network forward passes/s at 64^3 (bf16 matrix cores)",
+        "value": 1.0 / t_fwd,
+        "unit": "passes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_fwd * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (float32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "3-D conv encoder-decoder, channels 16-32-64, 3x3x3 kernels, "
+                               "64^3 grid, 8 input channels, batch 1 (training batch 4)",
+                   "forward_gflop": f_fwd / 1e9},
+        "roofline": {"bound": "mfma", "kernel": "whole forward pass (11 convolutions)",
+                     "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None},
+        "train_step_ms_batch4": t_train * 1e3,
+        "train_achieved_tflops": 3.0 * 4 * f_fwd / t_train / 1e12,
     }
     print(json.dumps(line), flush=True)
     return 0
