@@ -293,6 +293,12 @@ int vd_get_energy(vd_lattice* l, double out[4]);
  * (either pointer may be NULL).  Waits for the stream. */
 int vd_get_state(vd_lattice* l, float* pos, float* rot, int32_t mem);
 
+/* The finest state in float64 (Sec. 4: t_i = t_hat_i + d_i, R_i): the
+ * VD_FP64 state without rounding to float32 (a VD_FP32_FP64RED state
+ * widened), for checkpoints and comparisons at float64 precision.  pos[3N],
+ * rot[9N], either may be NULL.  Waits for the stream. */
+int vd_get_state64(vd_lattice* l, double* pos, double* rot, int32_t mem);
+
 /* Overwrite the finest state (checkpoint / resume).  rot may be NULL (then
  * R = I).  VD_EINVAL on non-finite input. */
 int vd_set_state(vd_lattice* l, const float* pos, const float* rot, int32_t mem);

@@ -51,7 +51,7 @@ EXPORTED = (
     "vd_net_train_step", "vd_associate", "vd_rigid_pose", "vd_set_depth_frame", "vd_get_pose",
     "vd_set_pose", "vd_track_frame", "vd_debug_associate", "vd_rigid_pose_noalloc",
     "vd_get_active", "vd_fuse_depth", "vd_get_tsdf", "vd_set_tsdf", "vd_extract_mesh",
-    "vd_debug_sort_pairs", "vd_debug_exclusive_scan", "vd_batch_tune",
+    "vd_debug_sort_pairs", "vd_debug_exclusive_scan", "vd_batch_tune", "vd_get_state64",
 )
 VD_TRACK_MAX_ITERS = 64
 VD_NOALLOC_MAX_SAMPLES = 1 << 30
@@ -222,6 +222,7 @@ def _load() -> C.CDLL:
         "vd_debug_sort_pairs": ([vp, vp, vp, vp, i64, i32, i32, vp], C.c_int),
         "vd_debug_exclusive_scan": ([vp, vp, i64, i32, vp], C.c_int),
         "vd_batch_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
+        "vd_get_state64": ([vp, vp, vp, i32], C.c_int),
         "vd_debug_prolong": ([vp, i32, vp, vp, i32], C.c_int),
         "vd_tune": ([vp, i32, C.POINTER(C.c_int32), dp], C.c_int),
         "vd_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
@@ -489,6 +490,15 @@ class Lattice:
         rot = np.empty((n, 3, 3), np.float32)
         _check(_lib.vd_get_state(self._h, pos.ctypes.data, rot.ctypes.data, VD_MEM_HOST),
                "vd_get_state")
+        return pos, rot
+
+    def get_state64(self):
+        """The finest state in float64: (positions (N, 3), rotations (N, 3, 3))."""
+        n = self.n_nodes()
+        pos = np.empty((n, 3), np.float64)
+        rot = np.empty((n, 3, 3), np.float64)
+        _check(_lib.vd_get_state64(self._h, pos.ctypes.data, rot.ctypes.data, VD_MEM_HOST),
+               "vd_get_state64")
         return pos, rot
 
     def set_state(self, pos, rot=None) -> None:

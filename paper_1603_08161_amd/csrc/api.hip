@@ -22,6 +22,13 @@
 static_assert(VD_TILE_KINDS == vd::kTileKinds, "tile kinds of vd.h and the kernels differ");
 
 namespace vd {
+// Finest state as float64 AoS (kernels.hip).
+template <typename T>
+hipError_t launch_state_out64(const LevelView<T>& L, const double* origin, double* pos,
+                              double* rot, hipStream_t s);
+}  // namespace vd
+
+namespace vd {
 namespace {
 
 #define VD_TRY(expr)                                  \
@@ -213,6 +220,7 @@ class ISolver {
   virtual int solve_frame(const vd_solve_opts* o, vd_solve_report* r) = 0;
   virtual int get_energy(double out[4]) = 0;
   virtual int get_state(float* pos, float* rot, int mem) = 0;
+  virtual int get_state64(double* pos, double* rot, int mem) = 0;
   virtual int set_state(const float* pos, const float* rot, int mem) = 0;
   virtual int level_info(int level, int dims[3], double* h) const = 0;
   virtual int debug_apply(int level, const float* p, float* ap, int mem) = 0;
@@ -563,6 +571,30 @@ class Solver final : public ISolver {
     VD_TRY(hipStreamSynchronize(stream_));
     for (int k = 0; k < 4; ++k) out[k] = h_sc_->energy[k];
     return VD_OK;
+  }
+
+  int get_state64(double* pos, double* rot, int mem) override {
+    if (mem != VD_MEM_HOST && mem != VD_MEM_DEVICE) return VD_EINVAL;
+    LevelData<T>& F = finest();
+    const size_t N = F.N;
+    const LevelView<T> V = F.view(desc_.w_arap);
+    if (mem == VD_MEM_DEVICE) {
+      VD_TRY(launch_state_out64<T>(V, desc_.origin, pos, rot, stream_));
+      VD_TRY(hipStreamSynchronize(stream_));
+      return VD_OK;
+    }
+    double* buf = nullptr;
+    VD_CHECK(pool_.alloc(&buf, 12 * N));
+    int rc = VD_OK;
+    if (launch_state_out64<T>(V, desc_.origin, pos ? buf : nullptr, rot ? buf + 3 * N : nullptr,
+                              stream_) != hipSuccess ||
+        (pos && hipMemcpyAsync(pos, buf, 24 * N, hipMemcpyDeviceToHost, stream_) != hipSuccess) ||
+        (rot && hipMemcpyAsync(rot, buf + 3 * N, 72 * N, hipMemcpyDeviceToHost, stream_) !=
+                    hipSuccess) ||
+        hipStreamSynchronize(stream_) != hipSuccess)
+      rc = VD_EHIP;
+    pool_.release(buf);
+    return rc;
   }
 
   int get_state(float* pos, float* rot, int mem) override {
@@ -2090,6 +2122,11 @@ int vd_set_constraints(vd_lattice* l, const vd_constraints* c) {
 int vd_solve_frame(vd_lattice* l, const vd_solve_opts* o, vd_solve_report* r) {
   if (!l) return VD_EINVAL;
   return l->impl->solve_frame(o, r);
+}
+
+int vd_get_state64(vd_lattice* l, double* pos, double* rot, int32_t mem) {
+  if (!l) return VD_EINVAL;
+  return l->impl->get_state64(pos, rot, mem);
 }
 
 int vd_get_energy(vd_lattice* l, double out[4]) {

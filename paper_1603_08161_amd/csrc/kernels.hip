@@ -635,6 +635,32 @@ hipError_t launch_state_io(const LevelView<T>& L, const double* o, float* pos, f
   return hipGetLastError();
 }
 
+// Finest state as float64 AoS: positions t_hat + d, rotations row-major.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_state_out64(LevelView<T> L, double ox, double oy,
+                                                        double oz, double* pos, double* rot) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.N) return;
+  const size_t N = L.N;
+  const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+  const double rest[3] = {ox + (double)L.h * x, oy + (double)L.h * y, oz + (double)L.h * z};
+  if (pos) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pos[3 * (size_t)i + k] = rest[k] + (double)L.d[k * N + i];
+  }
+  if (rot) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rot[9 * (size_t)i + k] = (double)L.rot[k * N + i];
+  }
+}
+
+template <typename T>
+hipError_t launch_state_out64(const LevelView<T>& L, const double* o, double* pos, double* rot,
+                              hipStream_t s) {
+  k_state_out64<T><<<blocks_for(L.N), kBlock, 0, s>>>(L, o[0], o[1], o[2], pos, rot);
+  return hipGetLastError();
+}
+
 // AoS float xyz <-> SoA T (used by the test entry points)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_add_delta(T* d, const float* delta, T h, int64_t n) {
@@ -696,6 +722,8 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
                                             unsigned char*, unsigned char*, hipStream_t);       \
   template hipError_t launch_state_io<T>(const LevelView<T>&, const double*, float*, float*,    \
                                          const float*, const float*, int, int*, hipStream_t);   \
+  template hipError_t launch_state_out64<T>(const LevelView<T>&, const double*, double*,        \
+                                            double*, hipStream_t);                              \
   template hipError_t launch_convert<T>(const float*, T*, int, hipStream_t);                    \
   template hipError_t launch_add_delta<T>(T*, const float*, double, int64_t, hipStream_t);      \
   template hipError_t launch_convert_back<T>(const T*, float*, int, hipStream_t);               \

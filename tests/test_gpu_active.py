@@ -41,15 +41,14 @@ def test_active_set_matches_oracle_on_every_level():
     assert 0.05 < lat.get_active(1)[1] / grids[1].n < 0.6
 
 
-# positions come back as float32 (about 1e-6 of the spacing at these
-# coordinates), so the float64 position gate is that rounding
-@pytest.mark.parametrize("precision,tol_e,tol_p", [("fp64", 1e-10, 2e-6), ("fp32", 1e-4, 1e-3)])
+# the float64 mode is compared through the float64 state export
+@pytest.mark.parametrize("precision,tol_e,tol_p", [("fp64", 1e-12, 1e-10), ("fp32", 1e-4, 1e-3)])
 def test_active_solve_matches_oracle(precision, tol_e, tol_p):
     sc = _patch(seed=2)
     lat = make_lattice(sc, active_set=True, precision=precision)
     rep = lat.solve_frame(reset=True, report=True)
     ref = active.solve_frame_active(sc)
-    pos = lat.get_state()[0].astype(np.float64)
+    pos = lat.get_state64()[0]
     e_rel = abs(rep["energy"][0] / ref["energy"][0] - 1.0)
     dp = np.abs(pos - ref["t"]).max() / sc.spec.spacing
     act = ref["active"]
@@ -76,13 +75,13 @@ def test_grid_growth_between_frames_matches_oracle():
     r2 = active.solve_frame_active(big, state=(r1["t"], r1["R"]), prev_active=r1["active"])
     assert layers == r2["layers"] >= 1
     rep = lat.solve_frame(report=True)
-    pos = lat.get_state()[0].astype(np.float64)
+    pos = lat.get_state64()[0]
     e_rel = abs(rep["energy"][0] / r2["energy"][0] - 1.0)
     dp = np.abs(pos - r2["t"]).max() / big.spec.spacing
     print(f"growth: {layers} layers, |M| {r1['active'].sum()} -> {r2['active'].sum()}, "
           f"E rel {e_rel:.2e}, max |dt|/h {dp:.2e}")
-    assert e_rel <= 1e-9
-    assert dp <= 2e-6  # float32 export of the positions
+    assert e_rel <= 1e-12
+    assert dp <= 1e-10
 
 
 def test_every_tile_kind_and_graph_give_the_same_bits():

@@ -15,19 +15,33 @@ from helpers import grids_of, make_lattice, rel_err, rotation_angle
 pytestmark = pytest.mark.gpu
 
 
-def _check_against_oracle(scene, lat_kw=None, e_tol=1e-4, x_tol=1e-3):
+def _check_against_oracle(scene, lat_kw=None, e_tol=1e-4, x_tol=1e-3, r_tol=1e-4):
+    """Gates: float32 mode as the target states (1e-4 energy, 1e-3 spacing)
+    and 1e-4 rad (measured up to 2.2e-6 rad at 64^3); float64 mode through
+    the float64 state export at 1e-12 / 1e-10 / 1e-10 rad (measured 4e-16,
+    5e-15 and 8e-15: rounding-order differences that truncated CG may
+    amplify by orders of magnitude)."""
+    if (lat_kw or {}).get("precision") == "fp64":
+        e_tol, x_tol, r_tol = 1e-12, 1e-10, 1e-10
     ref = oracle.solve_frame(scene)
     lat = make_lattice(scene, **(lat_kw or {}))
     rep = lat.solve_frame(report=True)
     assert not rep["bits"] & 16  # no grid-barrier timeout in a persistent CG loop
-    pos, rot = lat.get_state()
+    pos, rot = lat.get_state64()
     h = scene.spec.spacing
-    dx = np.abs(pos.astype(np.float64) - ref["t"]).max() / h
+    dx = np.abs(pos - ref["t"]).max() / h
     e_gpu, e_ref = rep["energy"], np.asarray(ref["energy"])
-    assert abs(e_gpu[0] / e_ref[0] - 1.0) < e_tol, (e_gpu, e_ref)
+    e_rel = abs(e_gpu[0] / e_ref[0] - 1.0)
+    dr = rotation_angle(rot, ref["R"]).max()
+    print(f"E rel {e_rel:.2e}, max |dt|/h {dx:.2e}, max rotation angle {dr:.2e} rad")
+    assert e_rel < e_tol, (e_gpu, e_ref)
     assert dx < x_tol, dx
-    assert rotation_angle(rot, ref["R"]).max() < 1e-2
+    assert dr < r_tol, dr
     np.testing.assert_allclose(lat.get_energy(), e_gpu, rtol=1e-12)
+    # the float32 export is the float64 state rounded
+    pos32, rot32 = lat.get_state()
+    np.testing.assert_array_equal(pos32, pos.astype(np.float32))
+    np.testing.assert_array_equal(rot32, rot.astype(np.float32))
     return lat, rep, ref
 
 
