@@ -595,7 +595,7 @@ def bench_batch(args) -> int:
                              "precision, hipGraph; the float64 part on a forked stream",
                    "tiles": batch_tiles},
         "oracle_gate": gate,
-        "roofline": {"bound": "hbm", "kernel": "batched fused CG iteration (k_cg_occ<float>) "
+        "roofline": {"bound": "hbm", "kernel": "batched fused CG iteration (k_cg<float>) "
                                                "on the finest level of the float32 lattices",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -221,8 +221,8 @@ __device__ __forceinline__ void arap_at(const LevelView<T>& L, const T (*sp)[TL:
 // and 3n+2 evaluating the blocks of dz = -1, 0, +1 of node n from that part of
 // the node's row (14 16-byte loads).  Lane 3n adds the three sums in fixed
 // order and leaves the result in LDS for the owner.  A node's sum does not
-// depend on which lane or round evaluates it, so every tile shape and both CG
-// forms give the same bits.
+// depend on which lane or round evaluates it, so the gradient pass and the CG
+// iteration give the same bits with every tile shape.
 
 constexpr int kPartsPerNode = 3;
 constexpr int kNodesPerWave = kWave / kPartsPerNode;  // 21; lane 63 idles
@@ -532,12 +532,12 @@ __device__ __forceinline__ void cg_scalars(const double* s, int n, Step<T>& alph
 }
 
 // One CG iteration m on the tile of workgroup w (body of k_cg and of the
-// persistent k_cg_loop).
-// PF: load the own nodes' preconditioner, displacement and previous direction
-// together with the halo (shorter dependent chain, more registers) instead of
-// at their use.  The data-block slots are loaded early in both forms: the
-// workgroup's list of data nodes needs them before the tile is staged.
-template <typename T, typename TL, bool FIRST, bool PF = true, bool MASK = false>
+// persistent k_cg_loop).  The own nodes' data-block slot, preconditioner,
+// displacement and previous direction are loaded together with the halo,
+// before the CG scalars, so that every workgroup pays one memory round trip
+// before it stages the tile (a form that loaded them at their use, for more
+// resident waves, was slower also on grids of several rounds of workgroups).
+template <typename T, typename TL, bool FIRST, bool MASK = false>
 __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL::HALO],
                                         T (&sr)[3][TL::HALO], unsigned char (&sm)[TL::HALO],
                                         DataShare<T, TL>& ds) {
@@ -635,14 +635,12 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
         (!act || act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)])) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
-      if (PF) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          own_q[kk][a] = dinv[a * N + i];
-          if (!FIRST) {
-            own_d[kk][a] = L.d[a * N + i];
-            own_pp[kk][a] = p_in[a * N + i];
-          }
+      for (int a = 0; a < 3; ++a) {
+        own_q[kk][a] = dinv[a * N + i];
+        if (!FIRST) {
+          own_d[kk][a] = L.d[a * N + i];
+          own_pp[kk][a] = p_in[a * N + i];
         }
       }
     }
@@ -677,10 +675,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       for (int a = 0; a < 3; ++a) {
         const size_t j = a * N + hi[h];
         p_out[j] = p3[a];
-        if (!FIRST) {
-          r_out[j] = r3[a];
-          if (!PF) L.d[j] = alpha.axpy(L.d[j], hp[h][a]);
-        }
+        if (!FIRST) r_out[j] = r3[a];
       }
     }
   }
@@ -704,8 +699,8 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       if (rank[kk] >= 0) o[a] += ds.d[a][e];
       const size_t j = a * N + i;
       ap_out[j] = o[a];
-      if (!FIRST && PF) L.d[j] = alpha.axpy(own_d[kk][a], own_pp[kk][a]);
-      const double q = (double)(PF ? own_q[kk][a] : dinv[j]), r = (double)sr[a][c],
+      if (!FIRST) L.d[j] = alpha.axpy(own_d[kk][a], own_pp[kk][a]);
+      const double q = (double)own_q[kk][a], r = (double)sr[a][c],
                    p = (double)sp[a][c];
       const double ap = (double)o[a];
       part[0] += r * q * r;
@@ -732,28 +727,8 @@ __global__ __launch_bounds__(TL::NT) void k_cg(Dispatch<T> D, int m, unsigned lo
   __shared__ DataShare<T, TL> ds;
   entry_stamp(stamp);
   const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST, true, MASK>(w, m, sp, sr, sm, ds);
+  cg_body<T, TL, FIRST, MASK>(w, m, sp, sr, sm, ds);
 }
-
-// The same iteration with the own-node values loaded at their use: fewer
-// registers, so more resident waves.  For grids larger than one round of
-// workgroups (batched lattices) occupancy hides more latency than the
-// register-held prefetches of k_cg.
-template <typename T, typename TL, bool FIRST, bool MASK>
-__global__ __launch_bounds__(TL::NT) void k_cg_occ(Dispatch<T> D, int m,
-                                                   unsigned long long* stamp) {
-  if (skipped(D)) return;
-  __shared__ T sp[3][TL::HALO];
-  __shared__ T sr[3][TL::HALO];
-  __shared__ unsigned char sm[TL::HALO];
-  __shared__ DataShare<T, TL> ds;
-  entry_stamp(stamp);
-  const Where<T> w = locate(D, xcd_remap(blockIdx.x, gridDim.x));
-  cg_body<T, TL, FIRST, false, MASK>(w, m, sp, sr, sm, ds);
-}
-
-// Workgroups that fit in one round on 256 CUs at the register use of k_cg.
-constexpr int kOneRoundBlocks = 1024;
 
 // Grid barrier of a launch whose workgroups are all resident: every
 // workgroup publishes its writes (agent-scope release), counts itself in,
@@ -816,9 +791,9 @@ __global__ __launch_bounds__(TL::NT) void k_cg_loop(Dispatch<T> D, int iters) {
   Scalars* sc = w.L.sc;
   for (int m = 0; m < iters; ++m) {
     if (m == 0)
-      cg_body<T, TL, true, true, MASK>(w, m, sp, sr, sm, ds);
+      cg_body<T, TL, true, MASK>(w, m, sp, sr, sm, ds);
     else
-      cg_body<T, TL, false, true, MASK>(w, m, sp, sr, sm, ds);
+      cg_body<T, TL, false, MASK>(w, m, sp, sr, sm, ds);
     grid_barrier(&sc->bar, (unsigned)(m + 1) * gridDim.x, &sc->bar_timeouts);
   }
   cg_final_tile<T, TL>(w, iters - 1);
@@ -846,22 +821,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
 
 template <typename T, typename TL>
 void launch_cg_t(int m, const Dispatch<T>& D, hipStream_t s, unsigned long long* stamp) {
-  if ((long)D.blocks * TL::NT > (long)kOneRoundBlocks * kBlock) {
-    if (D.masked) {
-      if (m == 0) k_cg_occ<T, TL, true, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-      else k_cg_occ<T, TL, false, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    } else {
-      if (m == 0) k_cg_occ<T, TL, true, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-      else k_cg_occ<T, TL, false, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    }
+  if (D.masked) {
+    if (m == 0) k_cg<T, TL, true, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    else k_cg<T, TL, false, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
   } else {
-    if (D.masked) {
-      if (m == 0) k_cg<T, TL, true, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-      else k_cg<T, TL, false, true><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    } else {
-      if (m == 0) k_cg<T, TL, true, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-      else k_cg<T, TL, false, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
-    }
+    if (m == 0) k_cg<T, TL, true, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
+    else k_cg<T, TL, false, false><<<D.blocks, TL::NT, 0, s>>>(D, m, stamp);
   }
 }
 
