@@ -186,7 +186,8 @@ def main() -> int:
         lat.set_constraints(*inputs)
         tiles, tile_us = lat.tune(iters=10)
         print(f"# tiles per level {tiles}; us per CG iteration incl. gradient pass [8x8x4, "
-              "8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024, 16x4x8/512]: "
+              "8x8x8, 32x8x4, 32x8x4/1024, 8x8x16/1024, 16x4x16/1024, 16x4x8/512, "
+              "8x8x4/512]: "
               + "; ".join("[" + ", ".join(f"{u:.2f}" for u in lv) + "]" for lv in tile_us),
               flush=True)
 

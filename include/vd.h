@@ -112,7 +112,7 @@ extern "C" {
                                          VD_FLAG_PERSIST) */
 
 #define VD_MAX_LEVELS 4
-#define VD_TILE_KINDS 7
+#define VD_TILE_KINDS 8
 #define VD_MAX_TRACE 512
 
 typedef struct vd_lattice vd_lattice;
@@ -140,7 +140,8 @@ typedef struct {
                                        3 = 32x8x4 (256 threads), 4 = 32x8x4
                                        (1024 threads), 5 = 8x8x16 (1024
                                        threads), 6 = 16x4x16 (1024 threads),
-                                       7 = 16x4x8 (512 threads) (see
+                                       7 = 16x4x8 (512 threads), 8 = 8x8x4
+                                       (512 threads, two per node) (see
                                        vd_tune) */
 } vd_lattice_desc;
 

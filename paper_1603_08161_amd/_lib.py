@@ -37,7 +37,7 @@ VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
 VD_REPORT_WARM_REJECTED = 8
 VD_REPORT_BARRIER_TIMEOUT = 16
 VD_MAX_LEVELS = 4
-VD_TILE_KINDS = 7
+VD_TILE_KINDS = 8
 VD_MAX_TRACE = 512
 
 EXPORTED = (

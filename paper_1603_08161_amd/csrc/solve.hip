@@ -116,6 +116,7 @@ int tile_blocks(int kind, int nx, int ny, int nz) {
     case 4: return nb(TileZ::TX, TileZ::TY, TileZ::TZ);
     case 5: return nb(TileY::TX, TileY::TY, TileY::TZ);
     case 6: return nb(TileH::TX, TileH::TY, TileH::TZ);
+    case 7: return nb(TileC::TX, TileC::TY, TileC::TZ);
     default: return nb(TileS::TX, TileS::TY, TileS::TZ);
   }
 }
@@ -134,9 +135,14 @@ struct TilePos {
     y0 = ty * TL::TY - 1;
     z0 = tz * TL::TZ - 1;
   }
+  // whether this thread owns nodes (tiles with more threads than nodes leave
+  // the last threads without; they stage the halo and evaluate data blocks)
+  __device__ __forceinline__ static bool owner() {
+    return TL::OWNERS == TL::NT || (int)threadIdx.x < TL::OWNERS;
+  }
   // LDS index of the k-th node owned by this thread
   __device__ __forceinline__ static int own(int k) {
-    const int t = threadIdx.x;
+    const int t = owner() ? (int)threadIdx.x : 0;
     const int lx = t % TL::TX + 1, ly = (t / TL::TX) % TL::TY + 1;
     const int lz = (t / (TL::TX * TL::TY)) * TL::NPT + k + 1;
     return lx + TL::HX * (ly + TL::HY * lz);
@@ -334,7 +340,7 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
       const int c = TilePos<TL>::own(kk);
       const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
       const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-      if (in_box(gx, gy, gz, L.nx, L.ny, L.nz))
+      if ((TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz)))
         any |= act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)];
     }
     if (!__syncthreads_or(any)) return;
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const int c = TilePos<TL>::own(kk);
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-    own_slot[kk] = in_box(gx, gy, gz, L.nx, L.ny, L.nz)
+    own_slot[kk] = (TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz))
                        ? L.node_slot[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)]
                        : -1;
   }
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const int c = TilePos<TL>::own(kk);
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    if (!(TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz))) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     if (act && !act[i]) {
       // not an unknown: zero gradient / product
@@ -476,6 +482,7 @@ hipError_t launch_stencil(int mode, const Dispatch<T>& D, const T* pin, T* out, 
     case 4: launch_stencil_t<T, TileZ>(mode, D, pin, out, s); break;
     case 5: launch_stencil_t<T, TileY>(mode, D, pin, out, s); break;
     case 6: launch_stencil_t<T, TileH>(mode, D, pin, out, s); break;
+    case 7: launch_stencil_t<T, TileC>(mode, D, pin, out, s); break;
     default: launch_stencil_t<T, TileS>(mode, D, pin, out, s); break;
   }
   return hipGetLastError();
@@ -566,7 +573,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       const int c = TilePos<TL>::own(kk);
       const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
       const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-      if (in_box(gx, gy, gz, L.nx, L.ny, L.nz))
+      if ((TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz)))
         any |= act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)];
     }
     if (!__syncthreads_or(any)) {
@@ -631,7 +638,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       own_d[kk][a] = T(0);
       own_pp[kk][a] = T(0);
     }
-    if (in_box(gx, gy, gz, L.nx, L.ny, L.nz) &&
+    if ((TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz)) &&
         (!act || act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)])) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
       own_slot[kk] = L.node_slot[i];
@@ -689,7 +696,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     const int c = TilePos<TL>::own(kk);
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz) || (act && !sm[c])) continue;
+    if (!(TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz)) || (act && !sm[c])) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     T o[3];
     arap_at<T, TL>(L, sp, c, gx, gy, gz, o[0], o[1], o[2], act ? sm : nullptr);
@@ -771,7 +778,7 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
     const int c = TilePos<TL>::own(kk);
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
-    if (!in_box(gx, gy, gz, L.nx, L.ny, L.nz)) continue;
+    if (!(TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz))) continue;
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     if (L.act && !L.act[i]) continue;
 #pragma unroll
@@ -840,6 +847,7 @@ hipError_t launch_cg(int m, const Dispatch<T>& D, hipStream_t s, unsigned long l
     case 4: launch_cg_t<T, TileZ>(m, D, s, stamp); break;
     case 5: launch_cg_t<T, TileY>(m, D, s, stamp); break;
     case 6: launch_cg_t<T, TileH>(m, D, s, stamp); break;
+    case 7: launch_cg_t<T, TileC>(m, D, s, stamp); break;
     default: launch_cg_t<T, TileS>(m, D, s, stamp); break;
   }
   return hipGetLastError();
@@ -862,6 +870,7 @@ void launch_cg_loop_t(int iters, const Dispatch<T>& D, hipStream_t s) {
     case 4: k_cg_loop<T, TileZ, MASK><<<D.blocks, TileZ::NT, 0, s>>>(D, iters); break;
     case 5: k_cg_loop<T, TileY, MASK><<<D.blocks, TileY::NT, 0, s>>>(D, iters); break;
     case 6: k_cg_loop<T, TileH, MASK><<<D.blocks, TileH::NT, 0, s>>>(D, iters); break;
+    case 7: k_cg_loop<T, TileC, MASK><<<D.blocks, TileC::NT, 0, s>>>(D, iters); break;
     default: k_cg_loop<T, TileS, MASK><<<D.blocks, TileS::NT, 0, s>>>(D, iters); break;
   }
 }

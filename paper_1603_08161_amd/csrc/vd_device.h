@@ -19,14 +19,17 @@ constexpr int kWave = 64;     // CDNA wavefront width
 constexpr int kXcds = 8;      // MI355X: 8 accelerator dies, workgroups dealt round-robin
 
 // Tiles of the stencil kernels: TX x TY x TZ nodes staged in LDS with a
-// one-node halo; NT threads, each owning NPT consecutive nodes along z.
+// one-node halo; NT threads, the first OWNERS of which own NPT consecutive
+// nodes along z each (with more threads than nodes, the others only stage
+// the halo and evaluate data blocks).
 template <int TX_, int TY_, int TZ_, int NT_ = kBlock>
 struct Tile {
   static constexpr int TX = TX_, TY = TY_, TZ = TZ_, NT = NT_;
   static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
   static constexpr int HALO = HX * HY * HZ;
   static constexpr int ZG = NT / (TX * TY);          // thread layers along z
-  static constexpr int NPT = TZ / ZG;                // nodes per thread
+  static constexpr int NPT = ZG >= TZ ? 1 : TZ / ZG; // nodes per owning thread
+  static constexpr int OWNERS = TX * TY * TZ / NPT;  // threads that own nodes
   static constexpr int HPT = (HALO + NT - 1) / NT;   // halo nodes staged per thread
 };
 // Tile kinds: small (most workgroups, best latency hiding), medium (half the
@@ -38,7 +41,10 @@ struct Tile {
 // observed surface facing the camera crosses fewer of their nodes, which
 // bounds the data-block work of the busiest workgroup), and the half-height
 // tall tile on 512 threads (two workgroups per CU share a CU's memory
-// bandwidth, so a tile heavy in data blocks is paired with an ordinary one).
+// bandwidth, so a tile heavy in data blocks is paired with an ordinary one),
+// and the small tile on 512 threads for the coarse levels, where nearly
+// every node carries data blocks: two threads per node, so the workgroup's
+// data-block work takes half the rounds.
 using TileS = Tile<8, 8, 4>;
 using TileM = Tile<8, 8, 8>;
 using TileW = Tile<32, 8, 4>;
@@ -46,7 +52,8 @@ using TileX = Tile<32, 8, 4, 1024>;
 using TileZ = Tile<8, 8, 16, 1024>;
 using TileY = Tile<16, 4, 16, 1024>;
 using TileH = Tile<16, 4, 8, 512>;
-constexpr int kTileKinds = 7;
+using TileC = Tile<8, 8, 4, 512>;
+constexpr int kTileKinds = 8;
 
 // Maps the hardware workgroup id to a logical tile id so that each XCD gets a
 // contiguous range of tiles (neighbouring tiles then share that XCD's L2).

@@ -90,7 +90,7 @@ def test_create_rejects_bad_descriptors_without_a_gpu():
         dict(good, num_levels=5),
         dict(good, dims=(3, 3, 3), num_levels=3),  # 3 -> 2 -> 1
         dict(good, origin=(0, float("inf"), 0)),
-        dict(good, tile=8),
+        dict(good, tile=9),
         dict(good, tile=-1),
     ]
     for c in cases:

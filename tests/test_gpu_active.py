@@ -89,7 +89,7 @@ def test_every_tile_kind_and_graph_give_the_same_bits():
     ref = make_lattice(sc, active_set=True)
     e_ref = ref.solve_frame(reset=True, report=True)["energy"]
     p_ref = ref.get_state()[0]
-    for tile in range(1, 8):
+    for tile in range(1, 9):
         for graph in (False, True):
             lat = make_lattice(sc, active_set=True, tiles=(tile, tile), graph=graph)
             e = lat.solve_frame(reset=True, report=True)["energy"]

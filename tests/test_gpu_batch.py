@@ -122,6 +122,7 @@ def test_batch_tuner_keeps_the_state_and_the_bits(graph):
     chosen tiles are set on every handle of a part, and the tuned batch still
     equals single solves with those tiles bit for bit."""
     from paper_1603_08161_amd import Batch
+    from paper_1603_08161_amd._lib import VD_TILE_KINDS
     scenes = _scenes(gn=2, pcg=6)
     precs = ["fp64" if k % 2 else "fp32" for k in range(len(scenes))]
     lats = [make_lattice(s, precision=p, graph=graph) for s, p in zip(scenes, precs)]
@@ -132,7 +133,7 @@ def test_batch_tuner_keeps_the_state_and_the_bits(graph):
     print("tuned tiles", tiles, "us/iteration fp32 finest", us[0, 2, :])
     assert set(tiles) == {"fp32", "fp64"}
     for name in tiles:
-        assert len(tiles[name]) == 3 and all(1 <= t <= 7 for t in tiles[name])
+        assert len(tiles[name]) == 3 and all(1 <= t <= VD_TILE_KINDS for t in tiles[name])
     assert np.all(us[0, :3] > 0) and np.all(us[1, :3] > 0)
     for lat, (p0, r0) in zip(lats, before):
         p1, r1 = lat.get_state()

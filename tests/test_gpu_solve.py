@@ -193,14 +193,14 @@ def test_empty_constraints():
     assert rep["energy"][0] == 0.0
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_every_tile_kind_matches_replica(tile):
     scene = make_tiny(seed=7, dims=(37, 21, 18), num_levels=3, gn=3, pcg=8, n_dense=1500,
                       n_sparse=30, spacing=0.5, origin=(0.0, 0.0, 0.0))
     _check_against_oracle(scene, {"tiles": (tile, tile, tile)})
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_every_node_with_data_blocks(tile):
     """Samples in every cell, so every node carries data blocks: each tile's
     data-block work takes several rounds of its workgroup (4 to 13 by tile
@@ -211,7 +211,7 @@ def test_every_node_with_data_blocks(tile):
     _check_against_oracle(scene, {"tiles": (tile,)})
 
 
-@pytest.mark.parametrize("tile", [1, 4, 6, 7])
+@pytest.mark.parametrize("tile", [1, 4, 6, 7, 8])
 def test_fp64_tile_kinds(tile):
     """The all-float64 mode on the larger tiles (their LDS doubles) and on a
     lattice whose every node carries data blocks."""
@@ -226,7 +226,8 @@ def test_autotuner_keeps_parity():
     ref = oracle.solve_frame(scene)
     lat = make_lattice(scene, graph=True)
     tiles, us = lat.tune(iters=5)
-    assert len(tiles) == 1 and 1 <= tiles[0] <= 7
+    from paper_1603_08161_amd._lib import VD_TILE_KINDS
+    assert len(tiles) == 1 and 1 <= tiles[0] <= VD_TILE_KINDS
     assert all(u > 0 for u in us[0])
     rep = lat.solve_frame(report=True)
     assert abs(rep["energy"][0] / ref["energy"][0] - 1.0) < 1e-4
@@ -255,7 +256,7 @@ def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, gra
     assert dx < (1e-5 if precision == "fp32" else 1e-6), dx
 
 
-@pytest.mark.parametrize("tile", [4, 6, 7])
+@pytest.mark.parametrize("tile", [4, 6, 7, 8])
 def test_persistent_cg_loop_on_large_tiles(tile):
     """The persistent loop with the 1024- and 512-thread tiles on a lattice
     whose every node carries data blocks (20-40 tiles, all resident)."""
