@@ -343,8 +343,9 @@ hipError_t launch_node_flags(const LevelView<T>& L, int* flags, hipStream_t s) {
 // Per node: the data part of row i of A as a 27-point block stencil,
 // A27[delta] = sum over adjacent active cells c (i = corner a of c, neighbour
 // = corner b, delta = b - a) of K_c[a][b]; stored at the node's compact slot
-// as a row A27r[slot][kA27Row] in three 16-byte-aligned parts by dz (one part
-// is one lane's share of the node in the stencil and CG kernels).  Also the
+// as a row A27r[slot][kA27Row]: three parts by dz (one part is one lane's
+// share of the node in the stencil and CG kernels), interleaved by 16-byte
+// chunks.  Also the
 // Jacobi diagonal 2 w_r |N_i| + diag(A27[0]), and the data right-hand side
 // b_i gathered from the cells.
 template <typename T>
@@ -390,15 +391,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble_nodes(LevelView<T> L, RowVi
       b[1] += bc[1];
       b[2] += bc[2];
     }
+    // entry q of part m (block (dx, dy) of dz = m - 1, zero padded) at chunk
+    // 3 (q / CW) + m, position q % CW
+    constexpr int CW = 16 / (int)sizeof(T);
     T* __restrict__ row_out = A27r + (size_t)slot * kA27Row;
-#pragma unroll
-    for (int dl = 0; dl < 27; ++dl)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) row_out[(dl / 9) * kA27Part + (dl % 9) * 6 + k] = acc[dl][k];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
-      for (int k = 54; k < kA27Part; ++k) row_out[m * kA27Part + k] = T(0);
+      for (int q = 0; q < kA27Part; ++q)
+        row_out[(3 * (q / CW) + m) * CW + q % CW] = q < 54 ? acc[m * 9 + q / 6][q % 6] : T(0);
     dg[0] = acc[13][0];
     dg[1] = acc[13][3];
     dg[2] = acc[13][5];

@@ -48,7 +48,7 @@ __device__ __forceinline__ Where<T> locate(const Dispatch<T>& D, int g) {
   int lo = 0;
   for (int base = 1; base < D.n; base += kWave) {
     const int idx = base + lane;
-    lo += __popcll(__ballot(idx < D.n && D.starts[idx] <= g));
+    lo += __popcll(__ballot(idx < D.n && glob<const int>(D.starts)[idx] <= g));
   }
   lo = __builtin_amdgcn_readfirstlane(lo);
   w.L = D.views[lo];
@@ -95,7 +95,7 @@ __device__ __forceinline__ void write_partials(double (&v)[K], double* out, int 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) s += lds[threadIdx.x * NW + w];
-    out[(size_t)threadIdx.x * stride + local] = s;
+    glob(out)[(size_t)threadIdx.x * stride + local] = s;
   }
 }
 
@@ -225,8 +225,10 @@ __device__ __forceinline__ void arap_at(const LevelView<T>& L, const T (*sp)[TL:
 // per wave, in (k, lane) order) and, once the tile is staged, the workgroup's
 // lanes take (node, part) items: per wave and round 21 nodes, lanes 3n, 3n+1
 // and 3n+2 evaluating the blocks of dz = -1, 0, +1 of node n from that part of
-// the node's row (14 16-byte loads).  Lane 3n adds the three sums in fixed
-// order and leaves the result in LDS for the owner.  A node's sum does not
+// the node's row (14 16-byte loads; the row interleaves the three parts'
+// chunks, so the three lanes of a node read one contiguous 48-byte span per
+// load).  Lane 3n adds the three sums in fixed order and leaves the result in
+// LDS for the owner.  A node's sum does not
 // depend on which lane or round evaluates it, so the gradient pass and the CG
 // iteration give the same bits with every tile shape.
 
@@ -274,27 +276,40 @@ __device__ __forceinline__ void eval_data_nodes(const LevelView<T>& L,
                                                 const T (*sp)[TL::HALO],
                                                 DataShare<T, TL>& ds) {
   using DS = DataShare<T, TL>;
+  constexpr int CW = 16 / (int)sizeof(T);  // entries per 16-byte chunk
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int part = lane % kPartsPerNode, nl = lane / kPartsPerNode;
-  int total = 0;
+  // first list position of every wave's segment (uniform: scalar registers)
+  int pre[DS::NW + 1];
+  pre[0] = 0;
 #pragma unroll
-  for (int u = 0; u < DS::NW; ++u) total += ds.cnt[u];
+  for (int w = 0; w < DS::NW; ++w) pre[w + 1] = pre[w] + __builtin_amdgcn_readfirstlane(ds.cnt[w]);
+  const int total = pre[DS::NW];
   for (int r0 = 0; r0 < total; r0 += DS::NW * kNodesPerWave) {
     const int v = r0 + wv * kNodesPerWave + nl;
     T o0 = T(0), o1 = T(0), o2 = T(0);
     int e = -1;
     if (nl < kNodesPerWave && v < total) {
+      // the segment holding list position v: the last one starting at or
+      // before it (segments are in wave order)
       int u = 0, before = 0;
-      while (v >= before + ds.cnt[u]) before += ds.cnt[u++];
+#pragma unroll
+      for (int x = 1; x < DS::NW; ++x)
+        if (v >= pre[x]) {
+          u = x;
+          before = pre[x];
+        }
       e = u * DS::SEG + (v - before);
       const int cz = ds.node[e] + TL::HX * TL::HY * (part - 1);
-      const T* __restrict__ A = static_cast<const T*>(__builtin_assume_aligned(
-          L.A27r + (size_t)ds.slot[e] * kA27Row + part * kA27Part, 16));
+      // entry x of the part: chunk 3 (x / CW) + part of the row
+      const gptr<const T> __restrict__ A = glob<const T>(static_cast<const T*>(
+          __builtin_assume_aligned(L.A27r + (size_t)ds.slot[e] * kA27Row + part * CW, 16)));
+      auto entry = [&](int x) { return A[kPartsPerNode * CW * (x / CW) + x % CW]; };
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
         const int q = cz + (j % 3 - 1) + TL::HX * (j / 3 - 1);
-        const T* __restrict__ blk = A + j * 6;
-        const T s0 = blk[0], s1 = blk[1], s2 = blk[2], s3 = blk[3], s4 = blk[4], s5 = blk[5];
+        const T s0 = entry(6 * j), s1 = entry(6 * j + 1), s2 = entry(6 * j + 2),
+                s3 = entry(6 * j + 3), s4 = entry(6 * j + 4), s5 = entry(6 * j + 5);
         const T q0 = sp[0][q], q1 = sp[1][q], q2 = sp[2][q];
         o0 += s0 * q0 + s1 * q1 + s2 * q2;
         o1 += s1 * q0 + s3 * q1 + s4 * q2;
@@ -327,11 +342,13 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
   const LevelView<T>& L = w.L;
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
-  const T* __restrict__ src = (MODE == kModeRhs) ? L.d : pin;
+  const gptr<const T> __restrict__ src = glob<const T>((MODE == kModeRhs) ? L.d : pin);
   // the CG solve that follows a gradient pass counts its grid barrier from 0
   if (MODE == kModeRhs && w.local == 0 && threadIdx.x == 0) L.sc->bar = 0u;
   // MASK: the optimised set M (a lattice of the launch may still have none)
-  const unsigned char* __restrict__ act = MASK ? L.act : nullptr;
+  const gptr<const unsigned char> __restrict__ act =
+      MASK ? glob<const unsigned char>(L.act) : nullptr;
+  const gptr<T> __restrict__ dst_out = glob<T>((MODE == kModeRhs) ? L.r : out);
   if (MODE == kModeRhs && act) {
     // a tile without points of M has no unknowns (its r is never read)
     int any = 0;
@@ -353,7 +370,7 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const int lx = c % TL::HX, ly = (c / TL::HX) % TL::HY, lz = c / (TL::HX * TL::HY);
     const int gx = t.x0 + lx, gy = t.y0 + ly, gz = t.z0 + lz;
     own_slot[kk] = (TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz))
-                       ? L.node_slot[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)]
+                       ? glob<const int>(L.node_slot)[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)]
                        : -1;
   }
   for (int k = threadIdx.x; k < TL::HALO; k += TL::NT) {
@@ -391,10 +408,9 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
     const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
     if (act && !act[i]) {
       // not an unknown: zero gradient / product
-      T* __restrict__ dst = (MODE == kModeRhs) ? L.r : out;
-      dst[i] = T(0);
-      dst[N + i] = T(0);
-      dst[2 * N + i] = T(0);
+      dst_out[i] = T(0);
+      dst_out[N + i] = T(0);
+      dst_out[2 * N + i] = T(0);
       continue;
     }
     T o0, o1, o2;
@@ -406,14 +422,15 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
       o2 += ds.d[2][e];
     }
     if (MODE == kModeApply) {
-      out[i] = o0;
-      out[N + i] = o1;
-      out[2 * N + i] = o2;
+      dst_out[i] = o0;
+      dst_out[N + i] = o1;
+      dst_out[2 * N + i] = o2;
       continue;
     }
     // rotation part of the ARAP gradient: for neighbour j = i + s*axis,
     // e_ij = -s h axis and (2I - R_i - R_j) e_ij = -s h (2 axis - R_i[:,k] - R_j[:,k]).
-    const T* __restrict__ rot = L.rot;
+    const gptr<const T> __restrict__ rot = glob<const T>(L.rot);
+    const gptr<const T> __restrict__ bnode = glob<const T>(L.bnode);
     T q0 = T(0), q1 = T(0), q2 = T(0);
     const int pos[3] = {gx, gy, gz};
     const int lim[3] = {L.nx, L.ny, L.nz};
@@ -440,14 +457,13 @@ __global__ __launch_bounds__(TL::NT) void k_stencil(Dispatch<T> D, const T* __re
         q2 += s * u2;
       }
     }
-    const T g0 = o0 - L.bnode[i] + L.wr * q0;
-    const T g1 = o1 - L.bnode[N + i] + L.wr * q1;
-    const T g2 = o2 - L.bnode[2 * N + i] + L.wr * q2;
-    T* __restrict__ dst = (MODE == kModeGrad) ? out : L.r;
+    const T g0 = o0 - bnode[i] + L.wr * q0;
+    const T g1 = o1 - bnode[N + i] + L.wr * q1;
+    const T g2 = o2 - bnode[2 * N + i] + L.wr * q2;
     const T sg = (MODE == kModeGrad) ? T(1) : T(-1);
-    dst[i] = sg * g0;
-    dst[N + i] = sg * g1;
-    dst[2 * N + i] = sg * g2;
+    dst_out[i] = sg * g0;
+    dst_out[N + i] = sg * g1;
+    dst_out[2 * N + i] = sg * g2;
   }
 }
 
@@ -552,17 +568,20 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
   const TilePos<TL> t(L.nx, L.ny, w.local);
   const size_t N = L.N;
   const bool odd = (m & 1) != 0;
-  const T* __restrict__ r_in = (FIRST || odd) ? L.r : L.r2;
-  T* __restrict__ r_out = odd ? L.r2 : L.r;
-  const T* __restrict__ p_in = odd ? L.pa : L.pb;
-  T* __restrict__ p_out = odd ? L.pb : L.pa;
-  const T* __restrict__ ap_in = odd ? L.ap : L.ap2;
-  T* __restrict__ ap_out = odd ? L.ap2 : L.ap;
+  const gptr<const T> __restrict__ r_in = glob<const T>((FIRST || odd) ? L.r : L.r2);
+  const gptr<T> __restrict__ r_out = glob<T>(odd ? L.r2 : L.r);
+  const gptr<const T> __restrict__ p_in = glob<const T>(odd ? L.pa : L.pb);
+  const gptr<T> __restrict__ p_out = glob<T>(odd ? L.pb : L.pa);
+  const gptr<const T> __restrict__ ap_in = glob<const T>(odd ? L.ap : L.ap2);
+  const gptr<T> __restrict__ ap_out = glob<T>(odd ? L.ap2 : L.ap);
   const double* s_in = odd ? L.scg0 : L.scg1;
   double* s_out = odd ? L.scg1 : L.scg0;
-  const T* __restrict__ dinv = L.dinv;
+  const gptr<const T> __restrict__ dinv = glob<const T>(L.dinv);
+  const gptr<T> __restrict__ dvec = glob<T>(L.d);
+  const gptr<const int> __restrict__ node_slot = glob<const int>(L.node_slot);
   // MASK: the optimised set M (a lattice of the launch may still have none)
-  const unsigned char* __restrict__ act = MASK ? L.act : nullptr;
+  const gptr<const unsigned char> __restrict__ act =
+      MASK ? glob<const unsigned char>(L.act) : nullptr;
   if (act) {
     // restricted to M: a tile without points of M has no unknowns; its
     // partials are zero.  Points outside M are read as 0 below and their
@@ -641,12 +660,12 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
     if ((TilePos<TL>::owner() && in_box(gx, gy, gz, L.nx, L.ny, L.nz)) &&
         (!act || act[gx + (size_t)L.nx * (gy + (size_t)L.ny * gz)])) {
       const size_t i = gx + (size_t)L.nx * (gy + (size_t)L.ny * gz);
-      own_slot[kk] = L.node_slot[i];
+      own_slot[kk] = node_slot[i];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         own_q[kk][a] = dinv[a * N + i];
         if (!FIRST) {
-          own_d[kk][a] = L.d[a * N + i];
+          own_d[kk][a] = dvec[a * N + i];
           own_pp[kk][a] = p_in[a * N + i];
         }
       }
@@ -706,7 +725,7 @@ __device__ __forceinline__ void cg_body(const Where<T>& w, int m, T (&sp)[3][TL:
       if (rank[kk] >= 0) o[a] += ds.d[a][e];
       const size_t j = a * N + i;
       ap_out[j] = o[a];
-      if (!FIRST) L.d[j] = alpha.axpy(own_d[kk][a], own_pp[kk][a]);
+      if (!FIRST) dvec[j] = alpha.axpy(own_d[kk][a], own_pp[kk][a]);
       const double q = (double)own_q[kk][a], r = (double)sr[a][c],
                    p = (double)sp[a][c];
       const double ap = (double)o[a];
@@ -771,8 +790,8 @@ __device__ __forceinline__ void cg_final_tile(const Where<T>& w, int last) {
   Step<T> alpha, beta;
   cg_scalars<T, TL::NT>(odd ? L.scg1 : L.scg0, L.ntiles, alpha, beta, L.sc, w.local == 0);
   const size_t N = L.N;
-  const T* __restrict__ p = odd ? L.pb : L.pa;
-  T* __restrict__ d = L.d;
+  const gptr<const T> __restrict__ p = glob<const T>(odd ? L.pb : L.pa);
+  const gptr<T> __restrict__ d = glob<T>(L.d);
 #pragma unroll
   for (int kk = 0; kk < TL::NPT; ++kk) {
     const int c = TilePos<TL>::own(kk);
@@ -820,8 +839,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_final(Dispatch<T> D, int last,
   const int i = w.local * kBlock + threadIdx.x;
   if (i >= L.N || (L.act && !L.act[i])) return;
   const size_t N = L.N;
-  const T* __restrict__ p = odd ? L.pb : L.pa;
-  T* __restrict__ d = L.d;
+  const gptr<const T> __restrict__ p = glob<const T>(odd ? L.pb : L.pa);
+  const gptr<T> __restrict__ d = glob<T>(L.d);
 #pragma unroll
   for (int a = 0; a < 3; ++a) d[a * N + i] = alpha.axpy(d[a * N + i], p[a * N + i]);
 }

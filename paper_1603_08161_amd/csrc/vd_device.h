@@ -63,6 +63,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
+// Global-memory (address space 1) view of a device pointer.  The lattice
+// arrays reach the kernels inside structs, where the compiler only sees
+// generic pointers and emits flat loads and stores.  The hardware counts a
+// flat access on the LDS/scalar-memory counter as well as on the vector-memory
+// counter, so every wait for an LDS or scalar-load result would also wait for
+// all vector loads in flight.  Global accesses keep the two apart (and take a
+// uniform base address in scalar registers).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T* p) {
+  return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------------------
 // reductions (float64 sums, fixed order => bitwise deterministic)
 // ---------------------------------------------------------------------------
@@ -128,9 +143,10 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds /* K * NT/
 // in the same fixed order (bitwise identical in all blocks).  No block of the
 // current kernel writes them, so the kernel boundary alone makes them
 // visible: no cross-workgroup fence is needed.
-__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n) {
+__device__ __forceinline__ double sum_partials(const double* __restrict__ pin, int n) {
   __shared__ double lds[kBlock / kWave];
   __shared__ double total;
+  const gptr<const double> __restrict__ p = glob(pin);
   double acc = 0.0;
   for (int b = threadIdx.x; b < n; b += kBlock) acc += p[b];
   acc = wave_sum(acc);
@@ -150,9 +166,10 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 // Sums of K partial arrays p + k*n (k < K) in one pass (one round of loads),
 // identical in every block; result valid in every thread.
 template <int K, int NT = kBlock>
-__device__ __forceinline__ void sum_partials_k(const double* __restrict__ p, int n,
+__device__ __forceinline__ void sum_partials_k(const double* __restrict__ pin, int n,
                                                double (&out)[K]) {
   constexpr int NW = NT / kWave;
+  const gptr<const double> __restrict__ p = glob(pin);
   __shared__ double lds[K * NW];
   __shared__ double total[K];
   double acc[K];

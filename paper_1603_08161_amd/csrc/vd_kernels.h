@@ -11,11 +11,13 @@ namespace vd {
 
 // Device-resident scalars of one level.  Written only by the last block of a
 // reduction kernel (or by a single thread), read by the next kernel.
-// Row of a node's 27 symmetric 3x3 data blocks in LevelView::A27r: three
-// parts (the 9 blocks of offset dz = -1, 0, +1, in (dx, dy) order), each 9 * 6
-// entries padded to kA27Part so that every part starts 16-byte aligned; entry
-// k of block delta = (dx, dy, dz) sits at (dz + 1) * kA27Part + ((dx + 1) +
-// 3 (dy + 1)) * 6 + k.  The two pad entries of a part hold 0.
+// Row of a node's 27 symmetric 3x3 data blocks in LevelView::A27r.  Part
+// m = dz + 1 holds the 9 blocks of offset dz in (dx, dy) order, 6 entries each
+// (xx, xy, xz, yy, yz, zz), padded with zeros to kA27Part entries: entry q of
+// part m is entry k = (dx + 1) + 3 (dy + 1), q = 6k + component.  The three
+// parts are interleaved by 16-byte chunks (C = 16 / sizeof(T) entries): entry
+// q of part m sits at (3 (q / C) + m) C + q % C, so the three lanes that
+// evaluate a node's parts read one contiguous span per chunk.
 constexpr int kA27Part = 56;
 constexpr int kA27Row = 3 * kA27Part;
 
