@@ -75,8 +75,9 @@ extern "C" {
                               replay */
 #define VD_FLAG_PERSIST 8u /* on levels of at most 128 tiles, run each CG
                               solve as one persistent launch with a grid
-                              barrier between iterations (default: one launch
-                              per CG iteration) */
+                              barrier between iterations (default: on levels
+                              of at most 16 tiles; one launch per CG
+                              iteration on larger ones) */
 #define VD_FLAG_ACTIVE_SET 16u /* optimise only the set M of Sec. 6-7: on each
                                   level the corners of the cells holding
                                   samples (the isosurface's points) plus their
@@ -88,6 +89,10 @@ extern "C" {
                                   from the previous build's: points that join
                                   it are initialised by extrapolating the
                                   field (Sec. 8; see vd_get_active) */
+#define VD_FLAG_ITERATIVE 32u /* one launch per CG iteration on every level
+                                 (overrides VD_FLAG_PERSIST and the default
+                                 persistent launch of levels of at most 16
+                                 tiles; the iterates are the same) */
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */

@@ -31,6 +31,7 @@ VD_FP32_FP64RED, VD_FP64 = 0, 1
 VD_MEM_HOST, VD_MEM_DEVICE = 0, 1
 VD_FLAG_GRAPH, VD_FLAG_TRACE, VD_FLAG_PROFILE, VD_FLAG_PERSIST = 1, 2, 4, 8
 VD_FLAG_ACTIVE_SET = 16
+VD_FLAG_ITERATIVE = 32
 VD_PROF_KINDS = 8
 PROF_NAMES = ("gradient", "cg_a", "cg_b", "rotation", "energy", "transfer", "cg_loop")
 VD_REPORT_PCG_GUARD, VD_REPORT_POLAR_FP64, VD_REPORT_POLAR_KEEP = 1, 2, 4
@@ -325,7 +326,7 @@ class Lattice:
     def __init__(self, dims, spacing, origin, num_levels=1, gn_iters=(5,), pcg_iters=(10,),
                  w_dense=1.0, w_sparse=10.0, w_arap=5.0, precision="fp32",
                  graph=False, trace=False, profile=False, tiles=None, persistent=False,
-                 active_set=False, stream: Optional[int] = None):
+                 active_set=False, iterative=False, stream: Optional[int] = None):
         d = LatticeDesc()
         for k in range(3):
             d.dims[k] = int(dims[k])
@@ -340,7 +341,8 @@ class Lattice:
         d.flags = ((VD_FLAG_GRAPH if graph else 0) | (VD_FLAG_TRACE if trace else 0)
                    | (VD_FLAG_PROFILE if profile else 0)
                    | (VD_FLAG_PERSIST if persistent else 0)
-                   | (VD_FLAG_ACTIVE_SET if active_set else 0))
+                   | (VD_FLAG_ACTIVE_SET if active_set else 0)
+                   | (VD_FLAG_ITERATIVE if iterative else 0))
         for k in range(VD_MAX_LEVELS):
             d.tile[k] = int(tiles[k]) if tiles is not None and k < len(tiles) else 0
         self.desc = d

@@ -1115,11 +1115,17 @@ class Solver final : public ISolver {
         for (int rep = 0; rep < 4; ++rep) {
           float ms = 0.0f;
           VD_TRY(hipMemcpyAsync(v.d, saved, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
-          // one position step: the gradient pass (which uses the same tile)
-          // and `iters` CG iterations
+          // one position step as the solve launches it: the gradient pass
+          // (which uses the same tile) and `iters` CG iterations with the
+          // final step
           VD_TRY(hipEventRecord(e0, stream_));
           VD_TRY(launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, stream_));
-          for (int m = 0; m < iters; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), stream_));
+          if (cg_loop(v)) {
+            VD_TRY(launch_cg_loop<T>(iters, tiles_of(V), stream_));
+          } else {
+            for (int m = 0; m < iters; ++m) VD_TRY(launch_cg<T>(m, tiles_of(V), stream_));
+            if (iters > 0) VD_TRY(launch_cg_final<T>(iters - 1, nodes_of(V), stream_));
+          }
           VD_TRY(hipEventRecord(e1, stream_));
           VD_TRY(hipEventSynchronize(e1));
           VD_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -1174,7 +1180,7 @@ class Solver final : public ISolver {
         VD_CHECK(timed(on, VD_PROF_ROTATION, s, [&] { return launch_polar<T>(nodes_of(V), s); }));
       }
       const int gn = desc_.gn_iters[l], pcg = desc_.pcg_iters[l];
-      const bool loop = persistent(v);
+      const bool loop = cg_loop(v);
       for (int k = 0; k < gn; ++k) {
         VD_CHECK(timed(on, VD_PROF_GRADIENT, s, [&] {
           return launch_stencil<T>(kModeRhs, tiles_of(V), nullptr, nullptr, s);
@@ -1212,10 +1218,19 @@ class Solver final : public ISolver {
     return VD_OK;
   }
 
-  // With VD_FLAG_PERSIST, levels whose tiles all fit at once run each CG
-  // solve as one persistent launch.
-  bool persistent(const LevelData<T>& v) const {
-    return (desc_.flags & VD_FLAG_PERSIST) && v.ntiles <= kPersistMaxTiles;
+  // Levels of at most this many tiles run each CG solve as one persistent
+  // launch by default (fewer launches; measured faster at 16^3, slower at
+  // 32^3 with 128 tiles).
+  static constexpr int kLoopDefaultMaxTiles = 16;
+
+  // Whether a level's CG solve runs as one persistent launch: with
+  // VD_FLAG_ITERATIVE never (one launch per CG iteration); with
+  // VD_FLAG_PERSIST on levels of at most kPersistMaxTiles tiles; by default on
+  // levels of at most kLoopDefaultMaxTiles tiles.
+  bool cg_loop(const LevelData<T>& v) const {
+    if (desc_.flags & VD_FLAG_ITERATIVE) return false;
+    if (desc_.flags & VD_FLAG_PERSIST) return v.ntiles <= kPersistMaxTiles;
+    return v.ntiles <= kLoopDefaultMaxTiles;
   }
 
   template <typename F>
@@ -1303,7 +1318,7 @@ class Solver final : public ISolver {
     const int pcg = desc_.pcg_iters[L_ - 1];
     auto g = [&](const Dispatch<T>& D) { return guarded(D, stop); };
     VD_TRY(launch_stencil<T>(kModeRhs, g(tiles_of(V)), nullptr, nullptr, s));
-    if (persistent(finest()) && pcg > 0) {
+    if (cg_loop(finest()) && pcg > 0) {
       VD_TRY(launch_cg_loop<T>(pcg, g(tiles_of(V)), s));
     } else {
       for (int m = 0; m < pcg; ++m) VD_TRY(launch_cg<T>(m, g(tiles_of(V)), s));

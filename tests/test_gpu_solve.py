@@ -236,24 +236,49 @@ def test_autotuner_keeps_parity():
 @pytest.mark.parametrize("maker,precision,graph", [(make_config0, "fp32", False),
                                                    (make_config0, "fp64", True),
                                                    (make_config1, "fp32", True)])
-def test_persistent_cg_loop_matches_per_iteration_launches(maker, precision, graph):
-    """With VD_FLAG_PERSIST, levels with at most 128 tiles run each CG solve as
-    one persistent launch with grid barriers; it computes the same iterates as
-    one launch per CG iteration (same operations, so equal up to
-    floating-point contraction choices) and never times out."""
+def test_cg_loops_match_per_iteration_launches(maker, precision, graph):
+    """Three ways to launch a level's CG solve: one launch per iteration
+    (VD_FLAG_ITERATIVE); the default, where a level of at most 16 tiles runs
+    the solve as one persistent launch with grid barriers; and
+    VD_FLAG_PERSIST, the persistent launch on levels of at most 128 tiles.
+    They compute the same iterates (same operations, so equal up to
+    floating-point contraction choices) and never time out."""
     from paper_1603_08161_amd import VD_REPORT_BARRIER_TIMEOUT
     scene = maker(0)
     out = {}
-    for persistent in (True, False):
-        lat = make_lattice(scene, precision=precision, graph=graph, persistent=persistent)
+    for mode, kw in (("iterative", dict(iterative=True)), ("default", {}),
+                     ("persistent", dict(persistent=True))):
+        lat = make_lattice(scene, precision=precision, graph=graph, **kw)
         rep = lat.solve_frame(report=True)
         assert not rep["bits"] & VD_REPORT_BARRIER_TIMEOUT
-        out[persistent] = (rep["energy"], lat.get_state()[0])
+        out[mode] = (rep["energy"], lat.get_state()[0])
     h = scene.spec.spacing
     tol = 1e-6 if precision == "fp32" else 1e-12
-    assert abs(out[True][0][0] / out[False][0][0] - 1.0) < tol
-    dx = np.abs(out[True][1].astype(np.float64) - out[False][1]).max() / h
-    assert dx < (1e-5 if precision == "fp32" else 1e-6), dx
+    for mode in ("default", "persistent"):
+        assert abs(out[mode][0][0] / out["iterative"][0][0] - 1.0) < tol, mode
+        dx = np.abs(out[mode][1].astype(np.float64) - out["iterative"][1]).max() / h
+        assert dx < (1e-5 if precision == "fp32" else 1e-6), (mode, dx)
+
+
+@pytest.mark.parametrize("active", [False, True])
+@pytest.mark.parametrize("tile", range(1, 9))
+def test_default_cg_loop_with_every_tile_kind(tile, active):
+    """The persistent CG loop (the default on a 16^3 level: 2 to 16 tiles with
+    every tile kind), with and without the optimised set M, against one
+    launch per CG iteration; two frames in a row, so the second starts from
+    the first one's barrier counters."""
+    from paper_1603_08161_amd import VD_REPORT_BARRIER_TIMEOUT
+    scene = make_config0(0)
+    out = {}
+    for iterative in (True, False):
+        lat = make_lattice(scene, tiles=(tile,), iterative=iterative, active_set=active)
+        for _ in range(2):
+            rep = lat.solve_frame(report=True)
+            assert not rep["bits"] & VD_REPORT_BARRIER_TIMEOUT
+        out[iterative] = (rep["energy"], lat.get_state()[0])
+    assert abs(out[False][0][0] / out[True][0][0] - 1.0) < 1e-6
+    dx = np.abs(out[False][1].astype(np.float64) - out[True][1]).max() / scene.spec.spacing
+    assert dx < 1e-5, dx
 
 
 @pytest.mark.parametrize("tile", [4, 6, 7, 8])
