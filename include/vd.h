@@ -72,7 +72,9 @@ extern "C" {
                               with VD_FLAG_GRAPH, device clock stamps captured
                               in the frame time the finest level's CG
                               iterations (class VD_PROF_CG_A) of every
-                              replay */
+                              replay, unless that level runs its CG solves
+                              as persistent launches (then nothing is
+                              stamped) */
 #define VD_FLAG_PERSIST 8u /* on levels of at most 128 tiles, run each CG
                               solve as one persistent launch with a grid
                               barrier between iterations (default: on levels
