@@ -291,6 +291,10 @@ __global__ __launch_bounds__(kBlock) void k_build_cells(RowView<T> R, T* K, cons
         const double* __restrict__ ua = s_u + ka * P;
         const double* __restrict__ ub = s_u + kb * P;
         int q = 0;
+        // unrolled so that 16 rows' LDS reads are in flight at once (one wave
+        // per SIMD: nothing else hides their latency); each accumulator still
+        // adds its rows in row order
+#pragma unroll 4
         for (; q + 4 <= cnt; q += 4) {
           a0 += ua[q] * ub[q];
           a1 += ua[q + 1] * ub[q + 1];

@@ -281,6 +281,25 @@ def test_default_cg_loop_with_every_tile_kind(tile, active):
     assert dx < 1e-5, dx
 
 
+@pytest.mark.parametrize("seed,graph", [(1, False), (2, True), (3, False)])
+def test_default_cg_loop_on_ragged_levels(seed, graph):
+    """A ragged 3-level lattice whose two coarse levels (4 and 1 tiles) run
+    their CG solves as persistent launches by default: the same iterates as
+    one launch per CG iteration, to the last bit, eager and graph-replayed
+    (a barrier that let a workgroup read a neighbour's stale halo shows up
+    here as a drift of 1e-3 of the spacing)."""
+    scene = make_tiny(seed=seed, dims=(19, 14, 10), num_levels=3, gn=3, pcg=8, n_dense=800,
+                      n_sparse=30, spacing=0.7, origin=(0.5, -2.0, 1.0))
+    out = {}
+    for iterative in (True, False):
+        lat = make_lattice(scene, iterative=iterative, graph=graph)
+        for _ in range(2):
+            rep = lat.solve_frame(reset=True, report=True)
+        out[iterative] = (rep["energy"], lat.get_state()[0])
+    np.testing.assert_array_equal(out[False][0], out[True][0])
+    np.testing.assert_array_equal(out[False][1], out[True][1])
+
+
 @pytest.mark.parametrize("tile", [4, 6, 7, 8])
 def test_persistent_cg_loop_on_large_tiles(tile):
     """The persistent loop with the 1024- and 512-thread tiles on a lattice
