@@ -94,7 +94,13 @@ extern "C" {
 #define VD_FLAG_ITERATIVE 32u /* one launch per CG iteration on every level
                                  (overrides VD_FLAG_PERSIST and the default
                                  persistent launch of levels of at most 16
-                                 tiles; the iterates are the same) */
+                                 tiles; the iterates are the same).  A
+                                 persistent launch needs all its workgroups
+                                 resident at once; if concurrent work on the
+                                 GPU prevents that, its barrier's bounded
+                                 wait gives up and the report carries
+                                 VD_REPORT_BARRIER_TIMEOUT: use this flag
+                                 there */
 
 /* ---- kernel classes timed under VD_FLAG_PROFILE ------------------------ */
 #define VD_PROF_GRADIENT 0  /* gradient / CG initialisation pass */
