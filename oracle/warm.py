@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .energy import Constraints
+from .energy import Assembled, Constraints
 from .lattice import Grid, trilinear
 
 
@@ -45,3 +45,18 @@ def features(grid: Grid, cons: Constraints, t_prev: np.ndarray, t_prev2=None) ->
     out[valid, 6] = num[valid] / den[valid] / grid.h
     out[:, 7] = valid.astype(np.float64)
     return out
+
+
+def exact_step(asm: Assembled, t: np.ndarray, R: np.ndarray, delta: np.ndarray):
+    """Minimiser along a direction of the energy at fixed rotations.  With R
+    fixed, E(t) = |J t - c(R)|^2 is quadratic in the positions (Sec. 7.1), so
+    E(t + s v) = E(t) + 2 s g.v + s^2 |J v|^2 with g = J^T r(t), and its
+    minimiser along v is s* = -g.v / |J v|^2 (0 when |J v| = 0).  t, delta:
+    (N, 3); returns (s*, t + s* delta)."""
+    t = np.asarray(t, np.float64).reshape(-1, 3)
+    v = np.asarray(delta, np.float64).reshape(-1)
+    g = asm.J.T @ asm.residual(t, R)
+    Jv = asm.J @ v
+    den = float(Jv @ Jv)
+    s = -float(g @ v) / den if den > 0.0 else 0.0
+    return s, t + s * v.reshape(-1, 3)

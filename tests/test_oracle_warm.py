@@ -88,3 +88,61 @@ def test_param_count_and_flatten_roundtrip():
     q = net.unflatten(v)
     for k in p:
         np.testing.assert_array_equal(p[k], q[k])
+
+
+def _tiny_system(seed):
+    from oracle.energy import prepare_constraints
+    from oracle.lattice import level_grids
+    from oracle.procrustes import rotation_step
+    from oracle.solver import LevelSystem, rest_state
+    from synth import make_tiny
+    scene = make_tiny(seed=seed, dims=(5, 4, 4), num_levels=1, gn=1, pcg=4, n_dense=120,
+                      n_sparse=6, spacing=0.5, origin=(0.1, -0.2, 0.3))
+    g = level_grids(scene.spec.dims, scene.spec.spacing, scene.spec.origin, 1)[0]
+    cons = prepare_constraints(scene, g)
+    t, R = rest_state(g)
+    rng = np.random.default_rng(seed)
+    t = t + 0.05 * rng.standard_normal(t.shape)
+    R = rotation_step(g, t, R)
+    return g, cons, LevelSystem(g, cons), t, R, rng
+
+
+def test_exact_step_recovers_the_position_minimiser():
+    """Along the direction to the exact minimiser of E at fixed R (a direct
+    sparse solve of A d = -g, another path than the step's formula) the step
+    is 1 and lands on that minimiser."""
+    from oracle.warm import exact_step
+    for seed in (1, 2):
+        g, cons, sysm, t, R, _ = _tiny_system(seed)
+        d = sysm.solve(-sysm.gradient(t, R), "direct", 0).reshape(-1, 3)
+        s, t_new = exact_step(sysm.asm, t, R, d)
+        assert abs(s - 1.0) < 1e-9, s
+        assert np.abs(t_new - (t + d)).max() < 1e-9
+
+
+def test_exact_step_is_the_minimum_along_the_line():
+    """E(t + s v), evaluated from the definitions eqs. (1)-(4), is smallest at
+    the returned s among a fine grid of steps, for random directions (the
+    exact minimum of a parabola through three of those values agrees)."""
+    from oracle.energy import energy_terms
+    from oracle.warm import exact_step
+    g, cons, sysm, t, R, rng = _tiny_system(3)
+    for _ in range(3):
+        v = rng.standard_normal(t.shape) * 0.1
+        s, _ = exact_step(sysm.asm, t, R, v)
+        E = lambda x: energy_terms(g, t + x * v, R, cons)[0]
+        e0 = E(s)
+        for x in s + np.linspace(-1.0, 1.0, 41) * max(abs(s), 0.1):
+            assert e0 <= E(x) + 1e-12
+        # vertex of the parabola through s - 1, s, s + 1
+        a, b, c = E(s - 1.0), e0, E(s + 1.0)
+        vertex = s - 0.5 * (c - a) / (a - 2 * b + c)
+        assert abs(vertex - s) < 1e-9 * max(1.0, abs(s))
+
+
+def test_exact_step_zero_direction():
+    """A zero direction (|J v| = 0) keeps the state: s = 0."""
+    from oracle.warm import exact_step
+    g, cons, sysm, t, R, _ = _tiny_system(4)
+    s, t_new = exact_step(sysm.asm, t, R, np.zeros_like(t))
+    assert s == 0.0 and np.array_equal(t_new, t)
