@@ -184,8 +184,9 @@ typedef struct {
  * Warm start (not in the paper; see vd_net.h for the network that produces
  * init_delta).  When init_delta is given the call first evaluates eq. (1) at
  * the plain initialisation (the previous frame's state) and at the predicted
- * one (finest displacement + spacing * init_delta, followed by one rotation
- * fit), and keeps the lower of the two.  The solve then runs from the kept
+ * one (finest displacement + spacing * init_delta, or with warm_mode 1 the
+ * minimum along init_delta, followed by one rotation fit), and keeps the
+ * lower of the two.  The solve then runs from the kept
  * state.  When energy_target > 0 the call runs finest-level flip-flop
  * iterations only, and stops after the first one whose energy is <=
  * energy_target, or after max_gn of them; with energy_target == 0 the full
@@ -204,7 +205,14 @@ typedef struct {
   double energy_target;     /* > 0: finest-level iterations until E <= it */
   int32_t max_gn;           /* iteration cap in target mode (0: the finest
                                level's gn_iters) */
-  int32_t reserved;
+  int32_t warm_mode;        /* with init_delta: 0 the predicted state is the
+                               finest displacement + spacing * init_delta;
+                               1 it is the minimum of eq. (1) along
+                               init_delta at the current rotations (E is
+                               quadratic in the positions: displacement +
+                               b * init_delta, b = -g.v / v.Av, g = J^T r,
+                               A = J^T J, v = init_delta), which can only
+                               lower E.  Other values: VD_EINVAL */
 } vd_solve_opts;
 
 /* Filled by vd_solve_frame when a report pointer is given (the call then

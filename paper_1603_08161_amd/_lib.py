@@ -96,7 +96,7 @@ class SolveOpts(C.Structure):
         ("init_delta", C.c_void_p),
         ("energy_target", C.c_double),
         ("max_gn", C.c_int32),
-        ("reserved", C.c_int32),
+        ("warm_mode", C.c_int32),
     ]
 
 
@@ -404,13 +404,15 @@ class Lattice:
                              scene.sparse_canon, scene.sparse_target)
 
     def solve_frame(self, reset: bool = False, report: bool = False, init_delta=None,
-                    energy_target: float = 0.0, max_gn: int = 0):
+                    energy_target: float = 0.0, max_gn: int = 0, warm_step: bool = False):
         """Solve one frame.  init_delta ([3][N] float32, units of the finest
-        spacing, numpy or CUDA tensor) asks for the judged warm start;
-        energy_target > 0 runs finest-level iterations until E <= it (at most
-        max_gn, 0 = the schedule's count)."""
+        spacing, numpy or CUDA tensor) asks for the judged warm start (with
+        warm_step: the exact line minimum of E along init_delta instead of
+        adding it); energy_target > 0 runs finest-level iterations until
+        E <= it (at most max_gn, 0 = the schedule's count)."""
         o = SolveOpts()
         o.reset_to_rest = 1 if reset else 0
+        o.warm_mode = 1 if warm_step else 0
         keep = None
         if init_delta is not None:
             (ptr,), mem, keep = _prep([init_delta])

@@ -26,6 +26,15 @@ namespace vd {
 template <typename T>
 hipError_t launch_state_out64(const LevelView<T>& L, const double* origin, double* pos,
                               double* rot, hipStream_t s);
+// Warm start's exact step (kernels.hip): float -> T copy, and d += b v with
+// b = -g.v / v.Av, the line minimum of E at fixed rotations; `part` holds
+// 2 * kWarmStepPartials doubles.
+constexpr int kWarmStepPartials = 1024;
+template <typename T>
+hipError_t launch_to_type(const float* in, T* out, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_warm_step(T* d, const T* g, const float* v, const T* av, int64_t n,
+                            double* part, hipStream_t s);
 }  // namespace vd
 
 namespace vd {
@@ -457,13 +466,14 @@ class Solver final : public ISolver {
     if (o && (!(o->energy_target >= 0.0) || !std::isfinite(o->energy_target) || o->max_gn < 0))
       return VD_EINVAL;
     if (warm && o->init_mem != VD_MEM_HOST && o->init_mem != VD_MEM_DEVICE) return VD_EINVAL;
+    if (o && o->warm_mode != 0 && o->warm_mode != 1) return VD_EINVAL;
     double e_init[2] = {0.0, 0.0};
     int warm_used = 0, gn_done = 0, reached = 0;
     if (reset && (warm || target)) {
       VD_TRY(launch_set_rest<T>(nodes_of(finest().view(desc_.w_arap)), stream_));
       reset = 0;
     }
-    if (warm) VD_CHECK(apply_warm(o->init_delta, o->init_mem, e_init, &warm_used));
+    if (warm) VD_CHECK(apply_warm(o->init_delta, o->init_mem, o->warm_mode, e_init, &warm_used));
     if (target) {
       const int cap = o->max_gn > 0 ? o->max_gn : desc_.gn_iters[L_ - 1];
       VD_CHECK(run_target(o->energy_target, cap, &gn_done, &reached));
@@ -1277,13 +1287,20 @@ class Solver final : public ISolver {
 
   // Warm start: evaluate eq. (1) at the plain initialisation and at
   // d + h * delta (after one rotation fit), keep the lower.
-  int apply_warm(const float* delta, int mem, double e[2], int* used) {
+  // step: 0 adds the prediction, 1 takes the exact line minimum along it
+  int apply_warm(const float* delta, int mem, int step, double e[2], int* used) {
     LevelData<T>& F = finest();
     const size_t N = F.N;
     VD_CHECK(ensure_debug());
     if (!warm_d_) {
       VD_CHECK(pool_.alloc(&warm_d_, 3 * N));
       VD_CHECK(pool_.alloc(&warm_rot_, 9 * N));
+    }
+    if (step && !warm_g_) {
+      VD_CHECK(pool_.alloc(&warm_g_, 3 * N));
+      VD_CHECK(pool_.alloc(&warm_v_, 3 * N));
+      VD_CHECK(pool_.alloc(&warm_av_, 3 * N));
+      VD_CHECK(pool_.alloc(&warm_part_, 2 * kWarmStepPartials));
     }
     const float* dd = delta;
     if (mem == VD_MEM_HOST) {
@@ -1297,8 +1314,18 @@ class Solver final : public ISolver {
     if (h_flags_[0]) return VD_EINVAL;
     VD_TRY(hipMemcpyAsync(warm_d_, F.d, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
     VD_TRY(hipMemcpyAsync(warm_rot_, F.rot, 9 * N * sizeof(T), hipMemcpyDeviceToDevice, stream_));
-    VD_TRY(launch_add_delta<T>(F.d, dd, F.h, 3 * (int64_t)N, stream_));
     const LevelView<T> V = F.view(desc_.w_arap);
+    if (step) {
+      // g = J^T r at the plain state, A v, then d += b v with the exact line
+      // minimum b = -g.v / v.Av at the current rotations (v in units of h)
+      VD_TRY(launch_to_type<T>(dd, warm_v_, 3 * (int64_t)N, stream_));
+      VD_TRY(launch_stencil<T>(kModeGrad, tiles_of(V), F.d, warm_g_, stream_));
+      VD_TRY(launch_stencil<T>(kModeApply, tiles_of(V), warm_v_, warm_av_, stream_));
+      VD_TRY(launch_warm_step<T>(F.d, warm_g_, dd, warm_av_, 3 * (int64_t)N, warm_part_,
+                                 stream_));
+    } else {
+      VD_TRY(launch_add_delta<T>(F.d, dd, F.h, 3 * (int64_t)N, stream_));
+    }
     VD_TRY(launch_polar<T>(nodes_of(V), stream_));
     VD_CHECK(finest_energy(&e[1]));
     *used = (e[1] <= e[0]) ? 1 : 0;
@@ -1599,6 +1626,8 @@ class Solver final : public ISolver {
   int n_stamped_ = 0, stamped_launches_ = 0;
   // warm start
   T *warm_d_ = nullptr, *warm_rot_ = nullptr;  // plain initialisation kept for the judge
+  T *warm_g_ = nullptr, *warm_v_ = nullptr, *warm_av_ = nullptr;  // exact warm step
+  double* warm_part_ = nullptr;
   hipGraphExec_t gn_graph_ = nullptr;          // one guarded finest-level iteration
   long gn_graph_gen_ = -1;
   int target_hint_ = 0;  // iterations the last target-mode call needed

@@ -680,6 +680,70 @@ hipError_t launch_add_delta(T* d, const float* delta, double h, int64_t n, hipSt
   return hipGetLastError();
 }
 
+// Exact step of a warm start along its predicted direction v (not in the
+// paper): with the rotations fixed E is quadratic in the displacement,
+// E(d + b v) = E(d) + 2 b g.v + b^2 v.Av with g = J^T r and A = J^T J
+// (Sec. 7.1), smallest at b = -g.v / v.Av.  k_warm_dots writes the block
+// partials of g.v and v.Av in float64; k_warm_step re-reduces them in every
+// block in the same order and applies d += b v (b = 0 when v.Av <= 0).
+constexpr int kWarmDotBlocks = 1024;  // partial pairs at most (the caller's buffer)
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_warm_dots(const T* __restrict__ g,
+                                                      const float* __restrict__ v,
+                                                      const T* __restrict__ av, int64_t n,
+                                                      double* part) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kBlock) {
+    const double vk = (double)v[k];
+    acc[0] += (double)g[k] * vk;
+    acc[1] += (double)av[k] * vk;
+  }
+  write_block_partials<2>(acc, part, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_warm_step(T* d, const float* __restrict__ v,
+                                                      int64_t n, const double* part,
+                                                      int nblocks) {
+  double s[2];
+  sum_partials_k<2>(part, nblocks, s);
+  const double b = s[1] > 0.0 ? -s[0] / s[1] : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * kBlock)
+    d[k] = (T)((double)d[k] + b * (double)v[k]);
+}
+
+// The direction as T (the A p pass reads T) and the step; `part` holds
+// 2 * kWarmDotBlocks doubles.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_type(const float* __restrict__ in, T* out,
+                                                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+template <typename T>
+hipError_t launch_to_type(const float* in, T* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_to_type<T><<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_warm_step(T* d, const T* g, const float* v, const T* av, int64_t n,
+                            double* part, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t want = (n + kBlock - 1) / kBlock;
+  const int nb = (int)(want < kWarmDotBlocks ? want : kWarmDotBlocks);
+  k_warm_dots<T><<<nb, kBlock, 0, s>>>(g, v, av, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_warm_step<T><<<nb, kBlock, 0, s>>>(d, v, n, part, nb);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_convert(const float* in, T* out, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -731,6 +795,9 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
                                             double*, hipStream_t);                              \
   template hipError_t launch_convert<T>(const float*, T*, int, hipStream_t);                    \
   template hipError_t launch_add_delta<T>(T*, const float*, double, int64_t, hipStream_t);      \
+  template hipError_t launch_to_type<T>(const float*, T*, int64_t, hipStream_t);                \
+  template hipError_t launch_warm_step<T>(T*, const T*, const float*, const T*, int64_t,        \
+                                          double*, hipStream_t);                                \
   template hipError_t launch_convert_back<T>(const T*, float*, int, hipStream_t);               \
   template hipError_t launch_fit_batch<T>(const float*, const float*, float*, int*, int64_t,    \
                                           hipStream_t);

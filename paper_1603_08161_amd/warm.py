@@ -264,6 +264,16 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
             cv.copy_(torch.from_numpy(((d_prev - d_prev2) / runner.h).reshape(-1)))
             rc = lat.solve_frame(report=True, init_delta=cv, energy_target=target,
                                  max_gn=max_gn)
+            # (d) the prediction as a direction: the exact minimum of E along
+            # it at fixed rotations, judged, same stopping rule
+            lat.set_state(pos0, rot0)
+            sync()
+            t = time.perf_counter()
+            lat.warm_features(prev2=p2, out=xbuf)
+            net.forward(xbuf, batch=1, out=out)
+            rs = lat.solve_frame(report=True, init_delta=out, energy_target=target,
+                                 max_gn=max_gn, warm_step=True)
+            t_step = time.perf_counter() - t
             net_err = float(((out - lab_dev(pos1)) ** 2).sum() / runner.n)
             recs.append(dict(seed=seed, frame=k, e_plain=e_plain, t_plain_ms=1e3 * t_plain,
                              e_init_plain=rw["init_energy"][0],
@@ -274,6 +284,9 @@ def evaluate(net: Net, pool, seeds, frames, n, device, max_gn: int = 16, log=pri
                              t_plain_target_ms=1e3 * t_pt, e_plain_target=float(rp["energy"][0]),
                              e_init_cv=rc["init_energy"][1], cv_used=rc["warm_used"],
                              gn_cv=rc["gn_done"], reached_cv=rc["target_reached"],
+                             e_init_step=rs["init_energy"][1], step_used=rs["warm_used"],
+                             gn_step=rs["gn_done"], reached_step=rs["target_reached"],
+                             t_step_ms=1e3 * t_step,
                              pred_mse=net_err,
                              cv_mse=float(((cv - lab_dev(pos1)) ** 2).sum() / runner.n),
                              zero_mse=float((lab_dev(pos1) ** 2).sum() / runner.n)))
@@ -313,6 +326,13 @@ def summarise(recs: List[Dict]) -> Dict:
         # initialisation over the judged prediction (> 1: the network helps)
         warm_start_factor=float(np.mean(a("t_plain_target_ms")) / np.mean(a("t_warm_ms"))),
         warm_start_gn_factor=float(np.mean(a("gn_plain_target")) / max(np.mean(a("gn_warm")), 1e-9)),
+        # the prediction used as a direction (exact line minimum), judged
+        step_init_energy_ratio_mean=float(np.mean(a("e_init_step") / a("e_init_plain"))),
+        step_used_frac=float(np.mean(a("step_used"))),
+        step_reached_frac=float(np.mean(a("reached_step"))),
+        gn_step_mean=float(np.mean(a("gn_step"))),
+        t_step_ms_mean=float(np.mean(a("t_step_ms"))),
+        warm_step_factor=float(np.mean(a("t_plain_target_ms")) / np.mean(a("t_step_ms"))),
         # the plain schedule over the warm path: credits the energy-target
         # stopping rule as much as the network
         speedup_vs_plain_schedule=float(np.mean(a("t_plain_ms")) / np.mean(a("t_warm_ms"))),

@@ -40,7 +40,15 @@ def test_trained_warm_start_on_a_held_out_sequence():
         if not r["warm_used"]:
             assert r["gn_warm"] == r["gn_plain_target"]
             assert r["e_warm"] == r["e_plain_target"]
+        # the exact step along the prediction never starts above the plain
+        # initialisation and reaches the target whenever that does
+        start = r["e_init_step"] if r["step_used"] else r["e_init_plain"]
+        assert start <= r["e_init_plain"]
+        assert r["reached_step"] >= r["reached_plain"]
     print(f"warm-start factor (plain-init time / warm time, same stopping rule): "
           f"{s['warm_start_factor']:.3f}; iterations {s['gn_plain_init_mean']:.2f} plain-init "
           f"vs {s['gn_warm_mean']:.2f} warm")
+    print(f"exact step along the prediction: factor {s['warm_step_factor']:.3f}, used on "
+          f"{s['step_used_frac']:.2f} of the frames, initial energy ratio "
+          f"{s['step_init_energy_ratio_mean']:.4f}, iterations {s['gn_step_mean']:.2f}")
     assert np.isfinite(s["warm_start_factor"]) and s["warm_start_factor"] > 0
