@@ -96,6 +96,52 @@ __device__ inline uint4 gather8(const ConvArgs& A, int b, int z, int y, int x, i
 // convolution (forward and backward data)
 // ---------------------------------------------------------------------------
 
+// Epilogue of a 16 x (16 NB) tile pair: bias, skip addend, ReLU / ReLU mask,
+// bfloat16 stores split over the concatenated outputs, or float32 output.
+template <int MB, int NB>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& A, const f32x4 (&acc)[MB][NB],
+                                              int64_t mbase, int lane) {
+  const int64_t M = (int64_t)A.batch * A.od * A.oh * A.ow;
+  // result tile: lane holds rows 4*(lane/16) + r, column lane % 16
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = mbase + i * 16 + 4 * (lane >> 4) + r;
+      if (m >= M) continue;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int co = j * 16 + (lane & 15);
+        float v = acc[i][j][r];
+        if (A.out_f32) {
+          if (co < A.cout) {
+            if (A.bias) v += A.bias[co];
+            const int64_t npb = (int64_t)A.od * A.oh * A.ow;
+            const int64_t b = m / npb, n = m - b * npb;
+            A.out_f32[(b * A.cout + co) * npb + n] = v;
+          }
+          continue;
+        }
+        if (co < A.c0) {
+          const size_t e = (size_t)m * A.c0 + co;
+          if (A.bias) v += A.bias[co];
+          if (A.add0) v += bf2f(A.add0[e]);
+          if (A.relu) v = fmaxf(v, 0.f);
+          if (A.mask0 && !bf_pos(A.mask0[e])) v = 0.f;
+          A.dst0[e] = f2bf(v);
+        } else if (co < A.c0 + A.c1) {
+          const size_t e = (size_t)m * A.c1 + (co - A.c0);
+          if (A.bias) v += A.bias[co];
+          if (A.add1) v += bf2f(A.add1[e]);
+          if (A.relu) v = fmaxf(v, 0.f);
+          if (A.mask1 && !bf_pos(A.mask1[e])) v = 0.f;
+          A.dst1[e] = f2bf(v);
+        }
+      }
+    }
+  }
+}
+
 template <int MB, int NB>
 __global__ __launch_bounds__(kBlock) void k_conv(ConvArgs A) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -139,44 +185,95 @@ __global__ __launch_bounds__(kBlock) void k_conv(ConvArgs A) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bw, acc[i][j], 0, 0, 0);
     }
   }
-  // result tile: lane holds rows 4*(lane/16) + r, column lane % 16
+  conv_epilogue<MB, NB>(A, acc, mbase, lane);
+}
+
+// Stride-1 convolutions whose workgroup block (64 MB voxels: 4 waves of MB
+// 16-voxel tiles) is R = 64 MB / ow whole rows of one (batch, z) plane: the
+// block's input (3 planes x (R + 2) rows x
+// (ow + 2) voxels x cin channels, zero outside the grid) is staged in LDS once,
+// and the 27 taps of every output voxel read it there instead of gathering
+// from global memory.  The fragments and the matrix ops, in their order, are
+// those of k_conv, so the results are the same bits.
+template <int MB, int NB>
+__global__ __launch_bounds__(kBlock) void k_conv_lds(ConvArgs A) {
+  constexpr int kConvBlockVox = (kBlock / kWave) * 16 * MB;
+  extern __shared__ uint4 s_in[];  // [voxel][cin / 8]
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int ow = A.ow, R = kConvBlockVox / ow, W2 = ow + 2, H2 = R + 2;
+  const int cg = A.cin >> 3;  // 16-byte channel groups per voxel
+  const int64_t blk0 = (int64_t)blockIdx.x * kConvBlockVox;
+  int64_t r = blk0 / ow;
+  const int y0 = (int)(r % A.oh);
+  r /= A.oh;
+  const int z = (int)(r % A.od), b = (int)(r / A.od);
+  const int nq = 3 * H2 * W2 * cg;
+  for (int q = threadIdx.x; q < nq; q += kBlock) {
+    const int v = q / cg, g = q - v * cg;
+    const int lx = v % W2, ly = (v / W2) % H2, lz = v / (W2 * H2);
+    const int sz = z + lz - 1, sy = y0 + ly - 1, sx = lx - 1;
+    uint4 val = {0u, 0u, 0u, 0u};
+    if (sz >= 0 && sz < A.sd && sy >= 0 && sy < A.sh && sx >= 0 && sx < A.sw) {
+      int c = g * 8;
+      const uint16_t* base = A.a;
+      int C = A.ca;
+      if (c >= A.ca) {
+        base = A.b;
+        C = A.cb;
+        c -= A.ca;
+      }
+      const size_t sv = (((size_t)b * A.sd + sz) * A.sh + sy) * A.sw + sx;
+      val = *reinterpret_cast<const uint4*>(base + sv * C + c);
+    }
+    s_in[q] = val;
+  }
+  __syncthreads();
+  const int64_t mbase = blk0 + wave * (16 * MB);
+  int vy[MB], vx[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
+    const int ml = wave * (16 * MB) + i * 16 + (lane & 15);
+    vy[i] = ml / ow;
+    vx[i] = ml - vy[i] * ow;
+  }
+  f32x4 acc[MB][NB];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t m = mbase + i * 16 + 4 * (lane >> 4) + r;
-      if (m >= M) continue;
+  for (int i = 0; i < MB; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int co = j * 16 + (lane & 15);
-        float v = acc[i][j][r];
-        if (A.out_f32) {
-          if (co < A.cout) {
-            if (A.bias) v += A.bias[co];
-            const int64_t npb = (int64_t)A.od * A.oh * A.ow;
-            const int64_t b = m / npb, n = m - b * npb;
-            A.out_f32[(b * A.cout + co) * npb + n] = v;
-          }
-          continue;
-        }
-        if (co < A.c0) {
-          const size_t e = (size_t)m * A.c0 + co;
-          if (A.bias) v += A.bias[co];
-          if (A.add0) v += bf2f(A.add0[e]);
-          if (A.relu) v = fmaxf(v, 0.f);
-          if (A.mask0 && !bf_pos(A.mask0[e])) v = 0.f;
-          A.dst0[e] = f2bf(v);
-        } else if (co < A.c0 + A.c1) {
-          const size_t e = (size_t)m * A.c1 + (co - A.c0);
-          if (A.bias) v += A.bias[co];
-          if (A.add1) v += bf2f(A.add1[e]);
-          if (A.relu) v = fmaxf(v, 0.f);
-          if (A.mask1 && !bf_pos(A.mask1[e])) v = 0.f;
-          A.dst1[e] = f2bf(v);
-        }
-      }
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  const uint4* __restrict__ W = A.w;
+  for (int ch = 0; ch < A.nchunk; ++ch) {
+    const int k0 = ch * 32 + kq;
+    const bool kin = k0 < A.ktot;
+    const int t = kin ? (k0 >> A.lcin) : 0, g = (k0 & (A.cin - 1)) >> 3;
+    const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+    bf16x8 af[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const uint4 v = kin ? s_in[((tz * H2 + vy[i] + ty) * W2 + vx[i] + tx) * cg + g]
+                          : uint4{0u, 0u, 0u, 0u};
+      af[i] = as_bf16x8(v);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bf16x8 bw = as_bf16x8(W[((size_t)ch * NB + j) * kWave + lane]);
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bw, acc[i][j], 0, 0, 0);
     }
   }
+  conv_epilogue<MB, NB>(A, acc, mbase, lane);
+}
+
+// LDS bytes k_conv_lds<MB, *> needs for A, or 0 where it does not apply.
+inline size_t conv_lds_bytes(const ConvArgs& A, int MB) {
+  const int block = (kBlock / kWave) * 16 * MB;
+  if (A.mode != kGatherPlain || A.stride != 1 || A.ow <= 0 || block % A.ow != 0) return 0;
+  const int R = block / A.ow;
+  if (A.oh % R != 0 || A.sd != A.od || A.sh != A.oh || A.sw != A.ow) return 0;
+  const size_t bytes = (size_t)3 * (R + 2) * (A.ow + 2) * (A.cin / 8) * 16;
+  return bytes <= 65536 ? bytes : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -787,6 +884,16 @@ class Net {
   hipError_t launch_conv(const ConvArgs& A) {
     const int64_t M = (int64_t)A.batch * A.od * A.oh * A.ow;
     const unsigned blocks = (unsigned)((M + 127) / 128);
+    // (4 tiles per wave, 256-voxel blocks, measured no faster than k_conv)
+    if (const size_t lds = conv_lds_bytes(A, 2)) {
+      switch (A.nb) {
+        case 1: k_conv_lds<2, 1><<<blocks, kBlock, lds, stream_>>>(A); break;
+        case 2: k_conv_lds<2, 2><<<blocks, kBlock, lds, stream_>>>(A); break;
+        case 4: k_conv_lds<2, 4><<<blocks, kBlock, lds, stream_>>>(A); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
     switch (A.nb) {
       case 1: k_conv<2, 1><<<blocks, kBlock, 0, stream_>>>(A); break;
       case 2: k_conv<2, 2><<<blocks, kBlock, 0, stream_>>>(A); break;
