@@ -57,6 +57,17 @@ def test_ragged_multilevel_matches_replica(seed):
     _check_against_oracle(scene)
 
 
+@pytest.mark.parametrize("dims,levels,precision", [((2, 2, 2), 1, "fp32"), ((2, 2, 2), 1, "fp64"),
+                                                  ((3, 3, 3), 2, "fp32"), ((3, 4, 5), 2, "fp64")])
+def test_smallest_lattices_match_replica(dims, levels, precision):
+    """The smallest lattices (one cell per axis, or a 2-node coarse level
+    under a 3-node one): one tile per level, the persistent CG loop with a
+    single workgroup, every sample in the last cell of each axis."""
+    scene = make_tiny(seed=40 + sum(dims), dims=dims, num_levels=levels, gn=3, pcg=6,
+                      n_dense=60, n_sparse=4, spacing=0.8, origin=(0.2, -0.1, 0.3))
+    _check_against_oracle(scene, {"precision": precision})
+
+
 def test_cfg1_matches_replica():
     """The 64^3, 3-level x 8 GN x 20 PCG frame the benchmark times."""
     lat, rep, ref = _check_against_oracle(make_config1(0))
