@@ -185,8 +185,9 @@ typedef struct {
  * init_delta).  When init_delta is given the call first evaluates eq. (1) at
  * the plain initialisation (the previous frame's state) and at the predicted
  * one (finest displacement + spacing * init_delta, or with warm_mode 1 the
- * minimum along init_delta, followed by one rotation fit), and keeps the
- * lower of the two.  The solve then runs from the kept
+ * minimum along init_delta, followed by one rotation fit; with
+ * VD_FLAG_ACTIVE_SET only the points of the optimised set move), and keeps
+ * the lower of the two.  The solve then runs from the kept
  * state.  When energy_target > 0 the call runs finest-level flip-flop
  * iterations only, and stops after the first one whose energy is <=
  * energy_target, or after max_gn of them; with energy_target == 0 the full

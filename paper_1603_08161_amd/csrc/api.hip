@@ -34,7 +34,11 @@ template <typename T>
 hipError_t launch_to_type(const float* in, T* out, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_warm_step(T* d, const T* g, const float* v, const T* av, int64_t n,
-                            double* part, hipStream_t s);
+                            double* part, const unsigned char* act, int64_t N, hipStream_t s);
+// d += h delta, on the points of the optimised set M only when act is given
+template <typename T>
+hipError_t launch_add_delta_in(T* d, const float* delta, double h, int64_t n,
+                               const unsigned char* act, int64_t N, hipStream_t s);
 }  // namespace vd
 
 namespace vd {
@@ -1321,10 +1325,10 @@ class Solver final : public ISolver {
       VD_TRY(launch_to_type<T>(dd, warm_v_, 3 * (int64_t)N, stream_));
       VD_TRY(launch_stencil<T>(kModeGrad, tiles_of(V), F.d, warm_g_, stream_));
       VD_TRY(launch_stencil<T>(kModeApply, tiles_of(V), warm_v_, warm_av_, stream_));
-      VD_TRY(launch_warm_step<T>(F.d, warm_g_, dd, warm_av_, 3 * (int64_t)N, warm_part_,
-                                 stream_));
+      VD_TRY(launch_warm_step<T>(F.d, warm_g_, dd, warm_av_, 3 * (int64_t)N, warm_part_, V.act,
+                                 (int64_t)N, stream_));
     } else {
-      VD_TRY(launch_add_delta<T>(F.d, dd, F.h, 3 * (int64_t)N, stream_));
+      VD_TRY(launch_add_delta_in<T>(F.d, dd, F.h, 3 * (int64_t)N, V.act, (int64_t)N, stream_));
     }
     VD_TRY(launch_polar<T>(nodes_of(V), stream_));
     VD_CHECK(finest_energy(&e[1]));

@@ -703,16 +703,39 @@ __global__ __launch_bounds__(kBlock) void k_warm_dots(const T* __restrict__ g,
   write_block_partials<2>(acc, part, gridDim.x);
 }
 
+// act (null: every point): with the optimised set M only its points move.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_warm_step(T* d, const float* __restrict__ v,
                                                       int64_t n, const double* part,
-                                                      int nblocks) {
+                                                      int nblocks,
+                                                      const unsigned char* __restrict__ act,
+                                                      int64_t N) {
   double s[2];
   sum_partials_k<2>(part, nblocks, s);
   const double b = s[1] > 0.0 ? -s[0] / s[1] : 0.0;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * kBlock)
-    d[k] = (T)((double)d[k] + b * (double)v[k]);
+    if (!act || act[k % N]) d[k] = (T)((double)d[k] + b * (double)v[k]);
+}
+
+// d += h delta on the points of the optimised set M only.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_delta_in(T* d, const float* __restrict__ delta,
+                                                         T h, int64_t n,
+                                                         const unsigned char* __restrict__ act,
+                                                         int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && act[i % N]) d[i] += h * (T)delta[i];
+}
+
+template <typename T>
+hipError_t launch_add_delta_in(T* d, const float* delta, double h, int64_t n,
+                               const unsigned char* act, int64_t N, hipStream_t s) {
+  if (!act) return launch_add_delta<T>(d, delta, h, n, s);
+  if (n == 0) return hipSuccess;
+  k_add_delta_in<T><<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(d, delta, (T)h, n,
+                                                                            act, N);
+  return hipGetLastError();
 }
 
 // The direction as T (the A p pass reads T) and the step; `part` holds
@@ -733,14 +756,14 @@ hipError_t launch_to_type(const float* in, T* out, int64_t n, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_warm_step(T* d, const T* g, const float* v, const T* av, int64_t n,
-                            double* part, hipStream_t s) {
+                            double* part, const unsigned char* act, int64_t N, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t want = (n + kBlock - 1) / kBlock;
   const int nb = (int)(want < kWarmDotBlocks ? want : kWarmDotBlocks);
   k_warm_dots<T><<<nb, kBlock, 0, s>>>(g, v, av, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_warm_step<T><<<nb, kBlock, 0, s>>>(d, v, n, part, nb);
+  k_warm_step<T><<<nb, kBlock, 0, s>>>(d, v, n, part, nb, act, N);
   return hipGetLastError();
 }
 
@@ -797,7 +820,9 @@ hipError_t launch_convert_back(const T* in, float* out, int n, hipStream_t s) {
   template hipError_t launch_add_delta<T>(T*, const float*, double, int64_t, hipStream_t);      \
   template hipError_t launch_to_type<T>(const float*, T*, int64_t, hipStream_t);                \
   template hipError_t launch_warm_step<T>(T*, const T*, const float*, const T*, int64_t,        \
-                                          double*, hipStream_t);                                \
+                                          double*, const unsigned char*, int64_t, hipStream_t); \
+  template hipError_t launch_add_delta_in<T>(T*, const float*, double, int64_t,                 \
+                                             const unsigned char*, int64_t, hipStream_t);       \
   template hipError_t launch_convert_back<T>(const T*, float*, int, hipStream_t);               \
   template hipError_t launch_fit_batch<T>(const float*, const float*, float*, int*, int64_t,    \
                                           hipStream_t);

@@ -65,3 +65,25 @@ def test_exact_warm_step_rejects_unknown_modes():
     o = _lib.SolveOpts()
     o.warm_mode = 2
     assert _lib._lib.vd_solve_frame(lat._h, _lib.C.byref(o), None) == _lib.VD_EINVAL
+
+
+@pytest.mark.parametrize("warm_step", [False, True])
+def test_warm_start_moves_only_the_optimised_set(warm_step):
+    """With the optimised set M, both warm-start forms move only the points
+    of M: the others keep their state through the frame (no iterations run
+    here, so the state after the call is the judged start)."""
+    scene = make_config0(4)
+    lat = make_lattice(scene, active_set=True)
+    lat.solve_frame()
+    mask, count, _ = lat.get_active()
+    assert 0 < count < mask.size
+    pos0, rot0 = lat.get_state()
+    rng = np.random.default_rng(4)
+    init = (0.05 * rng.standard_normal((3, mask.size))).astype(np.float32)
+    rep = lat.solve_frame(report=True, init_delta=init, warm_step=warm_step, energy_target=1e30)
+    assert rep["gn_done"] == 0
+    pos1, rot1 = lat.get_state()
+    np.testing.assert_array_equal(pos1[~mask], pos0[~mask])
+    np.testing.assert_array_equal(rot1[~mask], rot0[~mask])
+    if rep["warm_used"]:
+        assert np.abs(pos1[mask] - pos0[mask]).max() > 0
